@@ -1,0 +1,139 @@
+"""Independent FP64 CPU oracle for longitudinal macro-particle tracking.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package. It shares no code
+with the HIP path; the tracking arithmetic lives in ``ltrk_oracle.c`` (plain C,
+FP64, ``-O2 -ffp-contract=off``), this module only marshals NumPy arrays.
+
+The method (paper, section 1.1.2): each macro-particle's (z, delta) is
+integrated turn by turn by Euler-Cromer, leap-frog, fourth-order Ruth or
+Runge-Kutta; particles are independent (section 2.3). The single-harmonic
+map and its constants are documented in ``ltrk_oracle.c``.
+
+Every function here is pinned by tests against physics closed forms,
+textbook formulas, library routines or high-precision brute force; none is
+"parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+INTEGRATORS = {"euler_cromer": 0, "leapfrog": 1, "ruth4": 2, "rk4": 3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ltrk_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+RING_FIELDS = ("circumference_m", "harmonic", "voltage_V", "p0c_eV", "mass_eV",
+               "gamma_t", "charge_e")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc into ``oracle/_build/liboracle.so``."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+            "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            d = ctypes.c_double
+            p = ctypes.POINTER(ctypes.c_double)
+            lib.oracle_derive.argtypes = [d] * 7 + [p]
+            lib.oracle_derive.restype = ctypes.c_int
+            lib.oracle_track.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + [d] * 7 + \
+                [ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
+            lib.oracle_track.restype = ctypes.c_int
+            lib.oracle_moments.argtypes = [p, p, ctypes.c_int64, p]
+            lib.oracle_moments.restype = None
+            lib.oracle_max_threads.argtypes = []
+            lib.oracle_max_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ring_values(ring) -> list:
+    if isinstance(ring, dict):
+        return [float(ring[k]) for k in RING_FIELDS]
+    return [float(getattr(ring, k)) for k in RING_FIELDS]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+DERIVED_FIELDS = ("gamma", "beta", "eta", "A", "k", "D", "omega", "Qs", "Q_lf",
+                  "bucket_half_length", "bucket_height", "H_sep")
+
+
+def derive(ring) -> dict:
+    """Derived ring constants (FP64), keyed by ``DERIVED_FIELDS``."""
+    out = np.zeros(12)
+    rc = _load().oracle_derive(*_ring_values(ring), _ptr(out))
+    if rc != 0:
+        raise ValueError("invalid ring parameters")
+    return dict(zip(DERIVED_FIELDS, out.tolist()))
+
+
+def track(z, dp, turns: int, ring, integrator="leapfrog", substeps: int = 1,
+          with_moments: bool = True, threads: int = 0):
+    """Track copies of (z, dp) for ``turns`` turns.
+
+    Returns ``(z, dp, moments)`` with ``moments`` of shape ``[turns, 5]``
+    (mean_z, rms_z, mean_dp, rms_dp, emit_rms after each turn) or None.
+    ``substeps`` > 1 splits each turn into that many steps of length
+    1/substeps (used only by the convergence-order check).
+    """
+    integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    z = np.array(z, dtype=np.float64, copy=True, order="C").ravel()
+    dp = np.array(dp, dtype=np.float64, copy=True, order="C").ravel()
+    if z.shape != dp.shape:
+        raise ValueError("z and dp differ in length")
+    mom = np.empty((max(turns, 0), 5)) if with_moments else None
+    rc = _load().oracle_track(_ptr(z), _ptr(dp), z.size, int(turns), *_ring_values(ring),
+                              integ, int(substeps), _ptr(mom) if mom is not None else None,
+                              int(threads))
+    if rc != 0:
+        raise ValueError("invalid arguments to oracle_track")
+    return z, dp, mom
+
+
+def moments(z, dp) -> np.ndarray:
+    """Two-pass compensated population moments of one bunch (5 values)."""
+    z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+    dp = np.ascontiguousarray(dp, dtype=np.float64).ravel()
+    out = np.zeros(5)
+    _load().oracle_moments(_ptr(z), _ptr(dp), z.size, _ptr(out))
+    return out
+
+
+def hamiltonian(z, dp, ring) -> np.ndarray:
+    """Smooth single-harmonic Hamiltonian with one turn as the time unit,
+    H = -(D/2) dp^2 + (A/k)(cos(k z) - 1); H_sep = -2A/k on the separatrix."""
+    c = derive(ring)
+    z = np.asarray(z, dtype=np.float64)
+    dp = np.asarray(dp, dtype=np.float64)
+    return -0.5 * c["D"] * dp * dp + (c["A"] / c["k"]) * (np.cos(c["k"] * z) - 1.0)
+
+
+def max_threads() -> int:
+    """OpenMP threads the C oracle uses by default on this host."""
+    return int(_load().oracle_max_threads())

@@ -1,0 +1,294 @@
+/*
+ * Independent FP64 CPU oracle for longitudinal macro-particle tracking.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg do. It shares no code, header, table or constant with the
+ * HIP path.
+ *
+ * What it computes (paper, section 1.1.2 "The Longitudinal Plane"): every
+ * macro-particle carries a position z and a relative momentum deviation
+ * delta; both are integrated turn by turn, independently per particle, by an
+ * Euler-Cromer (first order), leap-frog (second order Verlet) or fourth-order
+ * Runge-Kutta / Ruth scheme. The paper names the schemes but prints no map;
+ * the map used here is the standard single-harmonic stationary RF bucket:
+ *
+ *   drift of weight w:  z     <- z - w * (eta * C) * delta
+ *   kick  of weight w:  delta <- delta + w * A * sin(k * z)
+ *   with A = q V / (beta p0 c)  (V in volts, p0 c in eV, so c cancels),
+ *        k = 2 pi h / C,  eta = 1/gamma_t^2 - 1/gamma^2.
+ *
+ * The loop order follows the paper's sequential C code (section 2.3): the
+ * turns outside, the particles inside. The particle loop may be split over
+ * OpenMP threads because particles are independent during tracking
+ * (section 2.3); results do not depend on the thread count.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math, no
+ * FMA contraction), so every operation below rounds exactly as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_EULER_CROMER = 0, OR_LEAPFROG = 1, OR_RUTH4 = 2, OR_RK4 = 3 };
+
+/* Machine constants of one ring, derived once (the paper's profile, section
+ * 2.2, shows the Python code re-deriving eta, beta, p0 on every call; they
+ * are fixed for a stationary bucket). */
+typedef struct {
+    double gamma, beta, eta, A, k, D;
+} or_consts;
+
+static int or_make_consts(double C, double h, double V, double p0c, double m,
+                          double gamma_t, double q, or_consts *c)
+{
+    if (!(C > 0.0) || !(h > 0.0) || !(p0c > 0.0) || !(m >= 0.0) ||
+        !(gamma_t > 0.0) || !isfinite(C) || !isfinite(h) || !isfinite(V) ||
+        !isfinite(p0c) || !isfinite(m) || !isfinite(gamma_t) || !isfinite(q))
+        return -1;
+    /* total energy E = sqrt(p^2 + m^2) (units of eV), gamma = E/m, beta = p/E */
+    double E = sqrt(p0c * p0c + m * m);
+    c->gamma = E / m; /* +inf for m = 0 */
+    c->beta = p0c / E;
+    c->eta = 1.0 / (gamma_t * gamma_t) - 1.0 / (c->gamma * c->gamma);
+    c->A = q * V / (c->beta * p0c);
+    c->k = 2.0 * M_PI * h / C;
+    c->D = c->eta * C;
+    return 0;
+}
+
+/* Derived quantities for reports and tests, in this order:
+ * gamma, beta, eta, A, k, D, omega_s (small-amplitude angular frequency per
+ * turn of the smooth motion), Q_s = omega_s / 2pi, Q of the linearised
+ * leap-frog map (cos mu = 1 - omega^2/2), bucket half-length C/(2h),
+ * bucket half-height, separatrix Hamiltonian H_sep.
+ * The smooth Hamiltonian with one turn as the time unit is
+ *   H(z, delta) = -(D/2) delta^2 + (A/k) (cos(k z) - 1),
+ * whose unstable fixed point z = C/(2h) gives H_sep = -2A/k. */
+int oracle_derive(double C, double h, double V, double p0c, double m,
+                  double gamma_t, double q, double out[12])
+{
+    or_consts c;
+    if (or_make_consts(C, h, V, p0c, m, gamma_t, q, &c) != 0)
+        return -1;
+    double w2 = c.A * c.k * c.D;
+    double omega = sqrt(fabs(w2));
+    out[0] = c.gamma;
+    out[1] = c.beta;
+    out[2] = c.eta;
+    out[3] = c.A;
+    out[4] = c.k;
+    out[5] = c.D;
+    out[6] = omega;
+    out[7] = omega / (2.0 * M_PI);
+    /* mu = 2 asin(omega/2) is the same angle as acos(1 - omega^2/2) */
+    out[8] = 2.0 * asin(omega / 2.0) / (2.0 * M_PI);
+    out[9] = C / (2.0 * h);
+    out[10] = 2.0 * sqrt(fabs(c.A / (c.k * c.D)));
+    out[11] = -2.0 * c.A / c.k;
+    return 0;
+}
+
+static void drift(const or_consts *c, double w, double *z, double dp)
+{
+    *z = *z - (w * c->D) * dp;
+}
+
+static void kick(const or_consts *c, double w, double z, double *dp)
+{
+    *dp = *dp + (w * c->A) * sin(c->k * z);
+}
+
+/* Fourth-order symplectic composition of Forest & Ruth (1990), identical to
+ * Yoshida's (1990) triple-jump of the leap-frog step. */
+static double ruth_theta(void)
+{
+    return 1.0 / (2.0 - cbrt(2.0));
+}
+
+/* One integration step of length w (in turns) of the chosen scheme. */
+static void step(const or_consts *c, int integrator, double w, double *z, double *dp)
+{
+    switch (integrator) {
+    case OR_EULER_CROMER: /* symplectic Euler: drift, then kick */
+        drift(c, w, z, *dp);
+        kick(c, w, *z, dp);
+        break;
+    case OR_LEAPFROG: /* Verlet: half drift, kick, half drift */
+        drift(c, 0.5 * w, z, *dp);
+        kick(c, w, *z, dp);
+        drift(c, 0.5 * w, z, *dp);
+        break;
+    case OR_RUTH4: {
+        double th = ruth_theta();
+        drift(c, 0.5 * th * w, z, *dp);
+        kick(c, th * w, *z, dp);
+        drift(c, 0.5 * (1.0 - th) * w, z, *dp);
+        kick(c, (1.0 - 2.0 * th) * w, *z, dp);
+        drift(c, 0.5 * (1.0 - th) * w, z, *dp);
+        kick(c, th * w, *z, dp);
+        drift(c, 0.5 * th * w, z, *dp);
+        break;
+    }
+    case OR_RK4: {
+        /* classical Runge-Kutta on dz/dn = -D delta, d(delta)/dn = A sin(k z) */
+        double z0 = *z, d0 = *dp;
+        double k1z = -c->D * d0, k1d = c->A * sin(c->k * z0);
+        double z2 = z0 + 0.5 * w * k1z, d2 = d0 + 0.5 * w * k1d;
+        double k2z = -c->D * d2, k2d = c->A * sin(c->k * z2);
+        double z3 = z0 + 0.5 * w * k2z, d3 = d0 + 0.5 * w * k2d;
+        double k3z = -c->D * d3, k3d = c->A * sin(c->k * z3);
+        double z4 = z0 + w * k3z, d4 = d0 + w * k3d;
+        double k4z = -c->D * d4, k4d = c->A * sin(c->k * z4);
+        *z = z0 + (w / 6.0) * (k1z + 2.0 * k2z + 2.0 * k3z + k4z);
+        *dp = d0 + (w / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+        break;
+    }
+    }
+}
+
+/* Neumaier's compensated summation (an improved Kahan-Babuska sum). */
+typedef struct {
+    double s, c;
+} or_sum;
+
+static void sum_add(or_sum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double sum_value(const or_sum *a)
+{
+    return a->s + a->c;
+}
+
+/* Fixed chunking of the particle axis: chunk partial sums are combined in
+ * chunk order, so the result does not depend on the thread count. */
+#define OR_CHUNK 4096
+
+/* Population moments of one bunch, two-pass and compensated:
+ * out = {mean_z, rms_z, mean_dp, rms_dp, emit_rms} with
+ *   rms_z^2 = sum (z - mean_z)^2 / n,  cov = sum (z - mean_z)(dp - mean_dp) / n,
+ *   emit_rms = sqrt(max(0, rms_z^2 rms_dp^2 - cov^2))  [metres].
+ * n = 0 gives NaN everywhere. */
+void oracle_moments(const double *z, const double *dp, int64_t n, double out[5])
+{
+    if (n <= 0) {
+        for (int i = 0; i < 5; ++i)
+            out[i] = NAN;
+        return;
+    }
+    int64_t nchunks = (n + OR_CHUNK - 1) / OR_CHUNK;
+    or_sum sz = {0, 0}, sd = {0, 0};
+#pragma omp parallel
+    {
+        /* each thread owns whole chunks; partials are merged in chunk order */
+#pragma omp for ordered schedule(static, 1)
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            or_sum cz = {0, 0}, cd = {0, 0};
+            int64_t hi = (ch + 1) * OR_CHUNK < n ? (ch + 1) * OR_CHUNK : n;
+            for (int64_t i = ch * OR_CHUNK; i < hi; ++i) {
+                sum_add(&cz, z[i]);
+                sum_add(&cd, dp[i]);
+            }
+#pragma omp ordered
+            {
+                sum_add(&sz, cz.s);
+                sum_add(&sz, cz.c);
+                sum_add(&sd, cd.s);
+                sum_add(&sd, cd.c);
+            }
+        }
+    }
+    double mz = sum_value(&sz) / (double)n;
+    double md = sum_value(&sd) / (double)n;
+    or_sum szz = {0, 0}, sdd = {0, 0}, szd = {0, 0};
+#pragma omp parallel
+    {
+#pragma omp for ordered schedule(static, 1)
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            or_sum czz = {0, 0}, cdd = {0, 0}, czd = {0, 0};
+            int64_t hi = (ch + 1) * OR_CHUNK < n ? (ch + 1) * OR_CHUNK : n;
+            for (int64_t i = ch * OR_CHUNK; i < hi; ++i) {
+                double a = z[i] - mz, b = dp[i] - md;
+                sum_add(&czz, a * a);
+                sum_add(&cdd, b * b);
+                sum_add(&czd, a * b);
+            }
+#pragma omp ordered
+            {
+                sum_add(&szz, czz.s);
+                sum_add(&szz, czz.c);
+                sum_add(&sdd, cdd.s);
+                sum_add(&sdd, cdd.c);
+                sum_add(&szd, czd.s);
+                sum_add(&szd, czd.c);
+            }
+        }
+    }
+    double vz = sum_value(&szz) / (double)n;
+    double vd = sum_value(&sdd) / (double)n;
+    double cov = sum_value(&szd) / (double)n;
+    double e2 = vz * vd - cov * cov;
+    out[0] = mz;
+    out[1] = sqrt(vz);
+    out[2] = md;
+    out[3] = sqrt(vd);
+    out[4] = sqrt(e2 > 0.0 ? e2 : 0.0);
+}
+
+/* Track n particles for `turns` turns in place. Each turn is `substeps`
+ * steps of length 1/substeps (substeps = 1 is the production map: one step
+ * per turn). If `moments` is not NULL it receives turns rows of 5 values,
+ * row t holding the moments after turn t+1. `threads` <= 0 means the OpenMP
+ * default. Returns 0, or -1 for invalid arguments. */
+int oracle_track(double *z, double *dp, int64_t n, int64_t turns, double C, double h,
+                 double V, double p0c, double m, double gamma_t, double q, int integrator,
+                 int substeps, double *moments, int threads)
+{
+    or_consts c;
+    if (n < 0 || turns < 0 || substeps < 1 || integrator < 0 || integrator > 3)
+        return -1;
+    if (or_make_consts(C, h, V, p0c, m, gamma_t, q, &c) != 0)
+        return -1;
+#ifdef _OPENMP
+    int saved = omp_get_max_threads();
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    double w = 1.0 / (double)substeps;
+    for (int64_t t = 0; t < turns; ++t) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int s = 0; s < substeps; ++s)
+                step(&c, integrator, w, &z[i], &dp[i]);
+        }
+        if (moments)
+            oracle_moments(z, dp, n, moments + 5 * t);
+    }
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    return 0;
+}
+
+/* Number of OpenMP threads a parallel region would use right now. */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
