@@ -1,0 +1,276 @@
+/*
+ * ltrk.h - C ABI of the MI355X longitudinal macro-particle tracker.
+ *
+ * The method (Oeftiger 2014, "Parallelisation of PyHEADTAIL", section 1.1.2):
+ * each macro-particle's longitudinal coordinates (z, delta) are integrated
+ * turn by turn through the RF bucket, independently per particle, by an
+ * Euler-Cromer, leap-frog (Verlet) or fourth-order Ruth / Runge-Kutta scheme.
+ * Particles are independent and turns are sequential (section 2.3). The map
+ * of one step of weight w (one turn = weight 1) is the single-harmonic
+ * stationary bucket:
+ *
+ *   drift:  z     <- z - w * eta * C * delta,      eta = 1/gamma_t^2 - 1/gamma^2
+ *   kick:   delta <- delta + w * (q V / (beta p0 c)) * sin(2 pi h z / C)
+ *
+ * After every turn the library can reduce the bunch to its population moments
+ * (mean and rms of z and delta, rms emittance), accumulated in FP64.
+ *
+ * Conventions for every entry point:
+ *   - Arrays named z, dp, z_comp, dp_comp, moments are DEVICE pointers owned
+ *     by the caller; the library never frees them. Arrays are contiguous
+ *     structure-of-arrays, one element per particle. A pointer that is not
+ *     device memory, or whose allocation is shorter than the stated length,
+ *     is rejected with LTRK_EINVAL before anything is enqueued.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Calls are
+ *     asynchronous: they return after enqueueing; device faults surface at the
+ *     caller's next synchronisation.
+ *   - Return 0 (LTRK_OK) or a negative code below; ltrk_last_error() gives a
+ *     thread-local message for the last failure. No C++ exception crosses
+ *     the ABI.
+ *   - n = 0 or turns = 0 is a successful no-op, except that with n = 0 and
+ *     turns > 0 the moment rows (if requested) are filled with NaN.
+ */
+#ifndef LTRK_H
+#define LTRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LTRK_ABI_VERSION 1
+
+/* Return codes. */
+#define LTRK_OK 0
+#define LTRK_EINVAL (-1)      /* invalid argument (sizes, pointers, ring, enums) */
+#define LTRK_ENOMEM (-2)      /* device or host allocation failed */
+#define LTRK_EDEVICE (-3)     /* a HIP runtime error; message holds hipGetErrorString */
+#define LTRK_EAGAIN (-4)      /* engine: no free slot or not enough budget right now */
+#define LTRK_EUNSUPPORTED (-5)
+
+/* Integration schemes (section 1.1.2). One scheme step per turn. */
+#define LTRK_EULER_CROMER 0   /* first order: drift(1), kick(1) */
+#define LTRK_LEAPFROG 1       /* second order: drift(1/2), kick(1), drift(1/2) */
+#define LTRK_RUTH4 2          /* fourth-order Forest-Ruth composition, 3 kicks */
+#define LTRK_RK4 3            /* classical Runge-Kutta, 4 force evaluations */
+
+/* State precisions. */
+#define LTRK_F64 0            /* z, dp in FP64 */
+#define LTRK_F32C 1           /* z, dp as FP32 hi plus FP32 Kahan compensation;
+                                 value = hi - comp. RF phase and moments in FP64 */
+
+/* Ring and beam parameters: circumference [m], harmonic number (integer
+ * valued, > 0), RF voltage [V], reference momentum p0 c [eV], rest energy
+ * m c^2 [eV] (>= 0), transition gamma (> 0), particle charge [e]. The sign of
+ * the voltage selects the stable phase: V > 0 is stable at z = 0 above
+ * transition (eta > 0); below transition pass a negated voltage. */
+typedef struct ltrk_ring {
+    double circumference_m;
+    double harmonic;
+    double voltage_V;
+    double p0c_eV;
+    double mass_eV;
+    double gamma_t;
+    double charge_e;
+} ltrk_ring;
+
+/* One moments row (40 bytes): population statistics (1/n) of the bunch.
+ * emit_rms = sqrt(max(0, rms_z^2 rms_dp^2 - cov(z,dp)^2)) in metres. */
+typedef struct ltrk_moments {
+    double mean_z;
+    double rms_z;
+    double mean_dp;
+    double rms_dp;
+    double emit_rms;
+} ltrk_moments;
+
+/* Derived constants of a ring, FP64. kick_amplitude A = q V / (beta p0 c);
+ * wavenumber k = 2 pi h / C [1/m]; slip_length D = eta C [m];
+ * omega_s = sqrt(A k D) [rad/turn] and q_s = omega_s / 2 pi (smooth motion);
+ * q_leapfrog solves cos(2 pi Q) = 1 - omega_s^2 / 2 (linearised leap-frog
+ * map); bucket_half_length = C / (2h); bucket_height = 2 sqrt(A / (k D));
+ * h_separatrix = -2 A / k for H = -(D/2) dp^2 + (A/k)(cos kz - 1).
+ * omega_s, q_s, q_leapfrog, bucket_height are NaN when A k D <= 0 (no
+ * stable bucket at z = 0). */
+typedef struct ltrk_derived {
+    double gamma;
+    double beta;
+    double eta;
+    double kick_amplitude;
+    double wavenumber;
+    double slip_length;
+    double omega_s;
+    double q_s;
+    double q_leapfrog;
+    double bucket_half_length;
+    double bucket_height;
+    double h_separatrix;
+} ltrk_derived;
+
+/* Host-only derivation of the ring constants above. EINVAL for a
+ * non-finite parameter, C <= 0, harmonic <= 0 or not integer valued,
+ * p0c <= 0, mass < 0 or gamma_t <= 0. */
+int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out);
+
+/* Track n particles for `turns` turns in place (FP64 state).
+ * z, dp: device arrays of n doubles, updated in place.
+ * moments: device array of `turns` rows or NULL; row t receives the moments
+ *   after turn t+1 (turn-0 moments: ltrk_moments_f64).
+ * integrator: LTRK_EULER_CROMER .. LTRK_RK4. */
+int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_ring* ring,
+                   int integrator, ltrk_moments* moments, void* stream);
+
+/* Same with the FP32 + Kahan-compensation state (LTRK_F32C). The four arrays
+ * of n floats are all state: z = z_hi - z_comp, dp = dp_hi - dp_comp. Start
+ * from comp = fl32(hi - value) (or zero); keep them between calls. */
+int ltrk_track_f32c(float* z, float* dp, float* z_comp, float* dp_comp, int64_t n,
+                    int64_t turns, const ltrk_ring* ring, int integrator,
+                    ltrk_moments* moments, void* stream);
+
+/* Moments of the current state (one row) into the device row `out`. */
+int ltrk_moments_f64(const double* z, const double* dp, int64_t n, ltrk_moments* out,
+                     void* stream);
+int ltrk_moments_f32c(const float* z, const float* dp, const float* z_comp,
+                      const float* dp_comp, int64_t n, ltrk_moments* out, void* stream);
+
+/* One bunch of a batched call: its own arrays (z_comp/dp_comp only for
+ * LTRK_F32C, else ignored), size, ring (own V and h) and moment rows
+ * (device, `turns` rows, or NULL). */
+typedef struct ltrk_bunch {
+    void* z;
+    void* dp;
+    void* z_comp;
+    void* dp_comp;
+    int64_t n;
+    ltrk_ring ring;
+    ltrk_moments* moments;
+} ltrk_bunch;
+
+/* Advance nb bunches of uneven size by `turns` turns with one scheme and one
+ * state precision: each launch sweeps a tile table covering every bunch, so
+ * all bunches move together. `bunches` is a HOST array of nb descriptors;
+ * the arrays it names are device memory. Results per bunch are those of
+ * ltrk_track_f64/f32c on that bunch with the same plan. */
+int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int integrator,
+                       int dtype, void* stream);
+
+/* Launch plan. turns_per_launch K: turns fused per kernel launch (1 = one
+ * launch per turn, the unfused form); block: threads per block (64, 128 or
+ * 256); ppl: particles per lane (1, 2, 4 or 8); use_graph: replay the launch
+ * sequence from a cached hipGraph (streams other than NULL only). */
+typedef struct ltrk_plan {
+    int32_t turns_per_launch;
+    int32_t block;
+    int32_t ppl;
+    int32_t use_graph;
+} ltrk_plan;
+
+/* Force one plan for all following calls of this process (NULL: back to
+ * automatic plans from the tuning cache or the built-in default). EINVAL for
+ * values outside the ranges above. */
+int ltrk_set_plan(const ltrk_plan* plan);
+
+/* The plan a call with these parameters would use now. */
+int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
+
+/* Time candidate plans on scratch particles of size n (on `stream`,
+ * synchronising it) and cache the fastest for (device, integrator, dtype,
+ * floor(log2 n)). `best` (host, may be NULL) receives it. */
+int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best);
+
+/* Save / load the tuning cache as text. */
+int ltrk_tune_cache_save(const char* path);
+int ltrk_tune_cache_load(const char* path);
+
+/* Per-launch timing with HIP events. While enabled, every tracking and
+ * finalize launch is bracketed by an event pair on its stream (graphs are
+ * bypassed so each launch is visible). ltrk_timing_take synchronises the
+ * recorded events, returns the totals and clears them. */
+typedef struct ltrk_timing {
+    int64_t track_launches;
+    double track_ms;
+    int64_t finalize_launches;
+    double finalize_ms;
+} ltrk_timing;
+
+int ltrk_timing_enable(int on);
+int ltrk_timing_take(ltrk_timing* out);
+
+/* ---- Serving engine: continuous batching of tracking jobs ----
+ * The engine owns a device arena of `hbm_budget_bytes` for job state and
+ * moment rows, and `max_slots` job slots. A job is admitted when a slot is
+ * free and its footprint fits in the arena; its state then stays on the device
+ * until it is retired. Each ltrk_engine_step is one launch over a tile table
+ * of every active job (mixed schemes and precisions) advancing each by
+ * min(k, turns left), plus one moments finalize launch. Jobs admitted between
+ * steps join the next step. Results equal those of ltrk_track_f64/f32c on the
+ * same job with the same particles-per-lane. Not thread-safe: one host thread
+ * drives an engine. */
+typedef struct ltrk_engine ltrk_engine;
+
+/* A job. z0/dp0 (and z0_comp/dp0_comp for LTRK_F32C) are HOST arrays of the
+ * initial state in the job's precision (double for F64, float for F32C),
+ * copied at admission. */
+typedef struct ltrk_job {
+    int64_t n;
+    int64_t turns;
+    ltrk_ring ring;
+    int32_t integrator;
+    int32_t dtype;
+    const void* z0;
+    const void* dp0;
+    const void* z0_comp;
+    const void* dp0_comp;
+} ltrk_job;
+
+typedef struct ltrk_engine_stats {
+    int32_t active_slots;
+    int32_t max_slots;
+    int64_t arena_bytes;
+    int64_t arena_free_bytes;
+    int64_t largest_free_block;
+    int64_t steps;
+    int64_t particle_turns;
+} ltrk_engine_stats;
+
+int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk_engine** out);
+/* Bytes of arena a job needs: state (16 B per particle) + moment rows (40 B
+ * per turn), each rounded up to 256 B. */
+int ltrk_engine_footprint(const ltrk_job* job, int64_t* bytes);
+/* Admit a job: LTRK_EAGAIN if no slot is free or the arena has no block large
+ * enough now; EINVAL if the job can never fit or is malformed. */
+int ltrk_engine_admit(ltrk_engine* e, const ltrk_job* job, int* slot);
+/* Advance every active job by up to k turns (1 <= k <= 4096). `stream` NULL
+ * uses the engine's own stream; otherwise the step is ordered after prior
+ * work on `stream` and `stream` waits for it. *advanced (may be NULL)
+ * receives the particle-turns enqueued. */
+int ltrk_engine_step(ltrk_engine* e, int k, void* stream, int64_t* advanced);
+/* done = 1 when all of the job's turns have been computed on the device. */
+int ltrk_engine_poll(ltrk_engine* e, int slot, int* done);
+/* Copy a finished job's final state and moment rows to HOST buffers (any may
+ * be NULL; comp arrays only for F32C), blocking until they are there. */
+int ltrk_engine_result(ltrk_engine* e, int slot, void* z, void* dp, void* z_comp,
+                       void* dp_comp, ltrk_moments* moments);
+/* Free a slot and its arena block (finished or not). */
+int ltrk_engine_retire(ltrk_engine* e, int slot);
+/* Stop a job: it takes no further turns; its slot stays until retired. */
+int ltrk_engine_cancel(ltrk_engine* e, int slot);
+int ltrk_engine_stats_get(ltrk_engine* e, ltrk_engine_stats* out);
+int ltrk_engine_destroy(ltrk_engine* e);
+
+/* Errors and lifetime. */
+const char* ltrk_strerror(int code);
+/* Copy the calling thread's last error message into buf (NUL terminated);
+ * returns the code of that error (0 if none). */
+int ltrk_last_error(char* buf, size_t len);
+/* Release per-device scratch, cached graphs and streams of this process. */
+int ltrk_shutdown(void);
+int ltrk_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LTRK_H */

@@ -1,0 +1,15 @@
+"""MI355X-native longitudinal macro-particle tracking (libltrk).
+
+Tracks macro-particles' (z, delta) turn by turn through a single-harmonic RF
+bucket with Euler-Cromer, leap-frog, fourth-order Ruth or RK4 schemes
+(Oeftiger 2014, section 1.1.2), with per-turn bunch moments, an FP32 +
+Kahan-compensated state, batched tracking of uneven bunches and a
+continuous-batching serving engine. All computation runs in the HIP library
+libltrk.so built for gfx950; this package is its ctypes binding.
+"""
+from ._binding import *  # noqa: F401,F403
+from ._binding import (EXPORTED, INTEGRATORS, DTYPES, Engine, EngineBusy, LtrkError, Ring,
+                       LIB_PATH)
+
+__all__ = [name for name in EXPORTED] + ["Engine", "EngineBusy", "LtrkError", "Ring",
+                                          "INTEGRATORS", "DTYPES", "LIB_PATH"]

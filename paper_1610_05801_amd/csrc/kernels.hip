@@ -1,0 +1,596 @@
+// HIP kernels of libltrk for gfx950 (CDNA4).
+//
+// The hot path is the per-particle turn map of Oeftiger 2014, section 1.1.2
+// (drift z -= w eta C delta, kick delta += w A sin(2 pi h z / C)) applied by
+// one of four schemes, with the turn loop fused inside the kernel (the
+// paper's "hybrid" design of section 2.3: a long enough in-register loop per
+// thread, re-launched from the host to cover all turns).
+//
+// Layout and mapping (MI355X-first):
+//   - state is structure-of-arrays in HBM; a wave tile owns 64 * P
+//     consecutive particles, lane l holding particles tile + p*64 + l, so each
+//     load/store instruction moves 64 consecutive elements;
+//   - P particles per lane give P independent dependency chains per lane
+//     (ILP for the FP64 VALU, which is the bound once turns are fused);
+//   - per-turn moment sums: each lane sums its P particles, the 5 lane sums
+//     of a turn go to a per-wave LDS row buffer, and every kFlushTurns turns
+//     the 15 rows are reduced by 4 lanes each and written as one double per
+//     (turn, moment, wave) to HBM. No block barrier and no atomics are used,
+//     so waves never wait on each other and every sum has a fixed order;
+//   - a separate finalize kernel adds the per-wave sums of each turn in a
+//     fixed order that depends only on the number of waves, so the moments
+//     are bit-identical for any K, block size or batching with the same P.
+//
+// The RF kick evaluates sin(k z) as sin(pi u), u = (2h/C) z in half
+// revolutions: n = rint(u), r = u - n is exact (Sterbenz) and |r| <= 1/2, the
+// polynomial of gen_sinpi.py gives sin(pi r), and (-1)^n restores the sign.
+// The reduction is branch-free and exact for any z, so particles that left
+// the bucket (large z) cost the same as the core.
+//
+// All arithmetic is written with explicit fma(); the library is compiled with
+// -ffp-contract=off so the rounding of every operation is fixed by the source.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "ltrk_device.h"
+#include "sinpi_coeffs.h"
+
+namespace ltrk {
+
+// ---------------------------------------------------------------------------
+// Elementary operations
+
+__device__ __forceinline__ double sin_pi_u(double u) {
+  const double n = __builtin_rint(u);
+  const double r = u - n;  // exact: |r| <= 1/2
+  const double s = r * r;
+  double p = kSinPiCoeff[kSinPiTerms - 1];
+#pragma unroll
+  for (int j = kSinPiTerms - 2; j >= 0; --j) p = __builtin_fma(p, s, kSinPiCoeff[j]);
+  const double y = r * p;
+  // (-1)^n: for |n| < 2^52 the parity of n is the last mantissa bit of
+  // |n| + 2^52; larger |u| has r = 0 and y = 0, where the sign is moot.
+  const double t = __builtin_fabs(n) + 0x1p52;
+  const uint64_t odd = (__builtin_bit_cast(uint64_t, t) & 1ull) << 63;
+  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, y) ^ odd);
+}
+
+// Kahan-compensated x += inc with the running compensation c (value = x - c).
+__device__ __forceinline__ void kahan_add(float& x, float& c, float inc) {
+  const float y = inc - c;
+  const float t = x + y;
+  c = (t - x) - y;
+  x = t;
+}
+
+// ---------------------------------------------------------------------------
+// One turn, FP64 state
+
+template <int INTEG>
+__device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) {
+  const double s = c.half_rev_per_m;
+  if constexpr (INTEG == kEulerCromer) {
+    z = __builtin_fma(c.nd[0], d, z);
+    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+  } else if constexpr (INTEG == kLeapfrog) {
+    z = __builtin_fma(c.nd[0], d, z);
+    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    z = __builtin_fma(c.nd[0], d, z);
+  } else if constexpr (INTEG == kRuth4) {
+    z = __builtin_fma(c.nd[0], d, z);
+    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    z = __builtin_fma(c.nd[1], d, z);
+    d = __builtin_fma(c.kw[1], sin_pi_u(z * s), d);
+    z = __builtin_fma(c.nd[1], d, z);
+    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    z = __builtin_fma(c.nd[0], d, z);
+  } else if constexpr (INTEG == kRk4) {
+    const double k1z = c.neg_D * d, k1d = c.A * sin_pi_u(z * s);
+    const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
+    const double k2z = c.neg_D * d2, k2d = c.A * sin_pi_u(z2 * s);
+    const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
+    const double k3z = c.neg_D * d3, k3d = c.A * sin_pi_u(z3 * s);
+    const double z4 = z + k3z, d4 = d + k3d;
+    const double k4z = c.neg_D * d4, k4d = c.A * sin_pi_u(z4 * s);
+    z = __builtin_fma(1.0 / 6.0, (k1z + 2.0 * k2z) + (2.0 * k3z + k4z), z);
+    d = __builtin_fma(1.0 / 6.0, (k1d + 2.0 * k2d) + (2.0 * k3d + k4d), d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One turn, FP32 + Kahan state. Drift increments are FP32 products of the FP32
+// momentum value; kick increments are FP64 (phase from the FP64 value
+// hi - comp, sin in FP64) rounded once to FP32. RK4 evaluates its stages in
+// FP64 from the FP64 state value and adds FP32-rounded increments.
+
+template <int INTEG>
+__device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float& dc,
+                                          const Coeffs& c) {
+  const double s = c.half_rev_per_m;
+  auto drift = [&](float ndf) { kahan_add(zh, zc, ndf * (dh - dc)); };
+  auto kick = [&](double kw) {
+    const double zv = static_cast<double>(zh) - static_cast<double>(zc);
+    kahan_add(dh, dc, static_cast<float>(kw * sin_pi_u(zv * s)));
+  };
+  if constexpr (INTEG == kEulerCromer) {
+    drift(c.nd_f[0]);
+    kick(c.kw[0]);
+  } else if constexpr (INTEG == kLeapfrog) {
+    drift(c.nd_f[0]);
+    kick(c.kw[0]);
+    drift(c.nd_f[0]);
+  } else if constexpr (INTEG == kRuth4) {
+    drift(c.nd_f[0]);
+    kick(c.kw[0]);
+    drift(c.nd_f[1]);
+    kick(c.kw[1]);
+    drift(c.nd_f[1]);
+    kick(c.kw[0]);
+    drift(c.nd_f[0]);
+  } else if constexpr (INTEG == kRk4) {
+    const double z = static_cast<double>(zh) - static_cast<double>(zc);
+    const double d = static_cast<double>(dh) - static_cast<double>(dc);
+    const double k1z = c.neg_D * d, k1d = c.A * sin_pi_u(z * s);
+    const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
+    const double k2z = c.neg_D * d2, k2d = c.A * sin_pi_u(z2 * s);
+    const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
+    const double k3z = c.neg_D * d3, k3d = c.A * sin_pi_u(z3 * s);
+    const double z4 = z + k3z, d4 = d + k3d;
+    const double k4z = c.neg_D * d4, k4d = c.A * sin_pi_u(z4 * s);
+    kahan_add(zh, zc, static_cast<float>((1.0 / 6.0) * ((k1z + 2.0 * k2z) + (2.0 * k3z + k4z))));
+    kahan_add(dh, dc, static_cast<float>((1.0 / 6.0) * ((k1d + 2.0 * k2d) + (2.0 * k3d + k4d))));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moment sums
+
+struct Sums {
+  double z, zz, d, dd, zd;
+};
+
+__device__ __forceinline__ void accumulate(Sums& s, double z, double d) {
+  s.z += z;
+  s.zz = __builtin_fma(z, z, s.zz);
+  s.d += d;
+  s.dd = __builtin_fma(d, d, s.dd);
+  s.zd = __builtin_fma(z, d, s.zd);
+}
+
+// Wave-scope ordering of LDS accesses (all lanes of one wave; no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void stage_sums(double* buf, int j, const Sums& s, int lane) {
+  double* r = buf + j * 5 * kRowStride + lane;
+  r[0 * kRowStride] = s.z;
+  r[1 * kRowStride] = s.zz;
+  r[2 * kRowStride] = s.d;
+  r[3 * kRowStride] = s.dd;
+  r[4 * kRowStride] = s.zd;
+}
+
+// Reduce `rows` staged LDS rows of 64 lane values each; row r goes to
+// out[r * stride]. Row r is summed by the 4 lanes r, r+16, r+32, r+48 over 16
+// values each (pairwise tree), then combined as (q0 + q1) + (q2 + q3).
+__device__ __forceinline__ void flush_rows(const double* buf, int rows, double* out,
+                                           int64_t stride, int lane) {
+  const int row = lane & 15;
+  const int quarter = lane >> 4;
+  double part = 0.0;
+  if (row < rows) {
+    const double2* src = reinterpret_cast<const double2*>(buf + row * kRowStride + quarter * 16);
+    double q[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double2 v = src[j];
+      q[j] = v.x + v.y;
+    }
+    q[0] = q[0] + q[1];
+    q[2] = q[2] + q[3];
+    q[4] = q[4] + q[5];
+    q[6] = q[6] + q[7];
+    q[0] = q[0] + q[2];
+    q[4] = q[4] + q[6];
+    part = q[0] + q[4];
+  }
+  double x = part + __shfl_xor(part, 16);
+  x = x + __shfl_xor(x, 32);
+  if (quarter == 0 && row < rows) out[static_cast<int64_t>(row) * stride] = x;
+}
+
+// ---------------------------------------------------------------------------
+// One wave tile for `turns` turns.
+
+template <int INTEG, int P, bool MOM>
+__device__ __forceinline__ void wave_f64(const BunchDev& b, int64_t w, int turns, int row0,
+                                         double* buf) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t first = w * static_cast<int64_t>(kWave * P) + lane;
+  double* __restrict__ zp = static_cast<double*>(b.z);
+  double* __restrict__ dpp = static_cast<double*>(b.dp);
+  double z[P], d[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t i = first + static_cast<int64_t>(p) * kWave;
+    z[p] = 0.0;
+    d[p] = 0.0;
+    if (i < b.n) {
+      z[p] = zp[i];
+      d[p] = dpp[i];
+    }
+  }
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
+  for (int t = 0; t < turns; t += kFlushTurns) {
+    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
+    for (int j = 0; j < nb; ++j) {
+      Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        turn_f64<INTEG>(z[p], d[p], b.c);
+        if constexpr (MOM) accumulate(s, z[p], d[p]);
+      }
+      if constexpr (MOM) stage_sums(buf, j, s, lane);
+    }
+    if constexpr (MOM) {
+      wave_sync();
+      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
+      wave_sync();
+    }
+  }
+  if constexpr (INTEG != kMeasureOnly) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t i = first + static_cast<int64_t>(p) * kWave;
+      if (i < b.n) {
+        zp[i] = z[p];
+        dpp[i] = d[p];
+      }
+    }
+  }
+}
+
+template <int INTEG, int P, bool MOM>
+__device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turns, int row0,
+                                          double* buf) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t first = w * static_cast<int64_t>(kWave * P) + lane;
+  float* __restrict__ zp = static_cast<float*>(b.z);
+  float* __restrict__ dpp = static_cast<float*>(b.dp);
+  float* __restrict__ zcp = static_cast<float*>(b.z_comp);
+  float* __restrict__ dcp = static_cast<float*>(b.dp_comp);
+  float zh[P], zc[P], dh[P], dc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t i = first + static_cast<int64_t>(p) * kWave;
+    zh[p] = zc[p] = dh[p] = dc[p] = 0.0f;
+    if (i < b.n) {
+      zh[p] = zp[i];
+      zc[p] = zcp[i];
+      dh[p] = dpp[i];
+      dc[p] = dcp[i];
+    }
+  }
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
+  for (int t = 0; t < turns; t += kFlushTurns) {
+    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
+    for (int j = 0; j < nb; ++j) {
+      Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        turn_f32c<INTEG>(zh[p], zc[p], dh[p], dc[p], b.c);
+        if constexpr (MOM)
+          accumulate(s, static_cast<double>(zh[p]) - static_cast<double>(zc[p]),
+                     static_cast<double>(dh[p]) - static_cast<double>(dc[p]));
+      }
+      if constexpr (MOM) stage_sums(buf, j, s, lane);
+    }
+    if constexpr (MOM) {
+      wave_sync();
+      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
+      wave_sync();
+    }
+  }
+  if constexpr (INTEG != kMeasureOnly) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t i = first + static_cast<int64_t>(p) * kWave;
+      if (i < b.n) {
+        zp[i] = zh[p];
+        zcp[i] = zc[p];
+        dpp[i] = dh[p];
+        dcp[i] = dc[p];
+      }
+    }
+  }
+}
+
+template <int INTEG, int DT, int P>
+__device__ __forceinline__ void run_wave(const BunchDev& b, int64_t w, int turns, int row0,
+                                         double* buf) {
+  if constexpr (DT == kF64) {
+    if (b.partials)
+      wave_f64<INTEG, P, true>(b, w, turns, row0, buf);
+    else
+      wave_f64<INTEG, P, false>(b, w, turns, row0, buf);
+  } else {
+    if (b.partials)
+      wave_f32c<INTEG, P, true>(b, w, turns, row0, buf);
+    else
+      wave_f32c<INTEG, P, false>(b, w, turns, row0, buf);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+
+// One bunch; block b covers wave tiles [b * wpb, (b+1) * wpb).
+template <int INTEG, int DT, int P>
+__global__ __launch_bounds__(kMaxBlock) void k_track_single(BunchDev b, int32_t row0) {
+  extern __shared__ double lds[];
+  const int wib = threadIdx.x >> 6;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
+  if (w >= b.waves) return;
+  run_wave<INTEG, DT, P>(b, w, b.turns, row0, lds + wib * kLdsDoublesPerWave);
+}
+
+// Many bunches, one scheme and precision; block -> tiles[blockIdx.x].
+template <int INTEG, int DT, int P>
+__global__ __launch_bounds__(kMaxBlock) void k_track_tiles(const BunchDev* __restrict__ bunches,
+                                                           const TileDev* __restrict__ tiles,
+                                                           int32_t turns, int32_t row0) {
+  extern __shared__ double lds[];
+  const TileDev t = tiles[blockIdx.x];
+  const BunchDev b = bunches[t.bunch];
+  const int wib = threadIdx.x >> 6;
+  const int64_t w = static_cast<int64_t>(t.wave0) + wib;
+  if (w >= b.waves) return;
+  run_wave<INTEG, DT, P>(b, w, turns, row0, lds + wib * kLdsDoublesPerWave);
+}
+
+// Engine step: every bunch carries its own scheme, precision and turn count.
+template <int P>
+__global__ __launch_bounds__(kMaxBlock) void k_track_mixed(const BunchDev* __restrict__ bunches,
+                                                           const TileDev* __restrict__ tiles) {
+  extern __shared__ double lds[];
+  const TileDev t = tiles[blockIdx.x];
+  const BunchDev b = bunches[t.bunch];
+  const int wib = threadIdx.x >> 6;
+  const int64_t w = static_cast<int64_t>(t.wave0) + wib;
+  if (!b.active || w >= b.waves || b.turns <= 0) return;
+  double* buf = lds + wib * kLdsDoublesPerWave;
+  const int key = b.integrator * 2 + b.dtype;
+  switch (key) {
+    case kEulerCromer * 2 + kF64: run_wave<kEulerCromer, kF64, P>(b, w, b.turns, 0, buf); break;
+    case kEulerCromer * 2 + kF32C: run_wave<kEulerCromer, kF32C, P>(b, w, b.turns, 0, buf); break;
+    case kLeapfrog * 2 + kF64: run_wave<kLeapfrog, kF64, P>(b, w, b.turns, 0, buf); break;
+    case kLeapfrog * 2 + kF32C: run_wave<kLeapfrog, kF32C, P>(b, w, b.turns, 0, buf); break;
+    case kRuth4 * 2 + kF64: run_wave<kRuth4, kF64, P>(b, w, b.turns, 0, buf); break;
+    case kRuth4 * 2 + kF32C: run_wave<kRuth4, kF32C, P>(b, w, b.turns, 0, buf); break;
+    case kRk4 * 2 + kF64: run_wave<kRk4, kF64, P>(b, w, b.turns, 0, buf); break;
+    case kRk4 * 2 + kF32C: run_wave<kRk4, kF32C, P>(b, w, b.turns, 0, buf); break;
+    default: break;
+  }
+}
+
+// Moments of rows of per-wave sums. One wave per row: lane l adds waves
+// l, l + 64, ... in order, then a xor butterfly over the 64 lanes (every lane
+// ends with the same, fixed-order total).
+__device__ __forceinline__ void finalize_row(const FinalizeDev& f, int row) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t W = f.waves;
+  const double* p = f.partials + static_cast<int64_t>(row) * 5 * W;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t w = lane; w < W; w += kWave) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] += p[m * W + w];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] += __shfl_xor(s[m], off);
+  }
+  if (lane == 0) {
+    const double nd = static_cast<double>(f.n);
+    const double mz = s[0] / nd;
+    const double md = s[2] / nd;
+    double vz = s[1] / nd - mz * mz;
+    double vd = s[3] / nd - md * md;
+    const double cov = s[4] / nd - mz * md;
+    vz = vz > 0.0 ? vz : 0.0;
+    vd = vd > 0.0 ? vd : 0.0;
+    const double e2 = vz * vd - cov * cov;
+    ltrk_moments o;
+    o.mean_z = mz;
+    o.rms_z = __builtin_sqrt(vz);
+    o.mean_dp = md;
+    o.rms_dp = __builtin_sqrt(vd);
+    o.emit_rms = __builtin_sqrt(e2 > 0.0 ? e2 : 0.0);
+    f.out[row] = o;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_single(FinalizeDev f) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row < f.rows) finalize_row(f, row);
+}
+
+// blockIdx.y selects the bunch; rows [0, min(rows, f.rows)) are reduced and
+// written to f.out[out_row0 + row].
+__global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeDev* __restrict__ fs,
+                                                        int32_t rows, int64_t out_row0) {
+  FinalizeDev f = fs[blockIdx.y];
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (f.out == nullptr || row >= rows || row >= f.rows) return;
+  f.out += out_row0;
+  finalize_row(f, row);
+}
+
+__global__ void k_fill_nan(ltrk_moments* out, int64_t rows) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < rows) {
+    const double nan = __builtin_nan("");
+    out[i] = ltrk_moments{nan, nan, nan, nan, nan};
+  }
+}
+
+// Deterministic filler for the tuner's scratch particles.
+__global__ void k_fill_probe(double* z, double* dp, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    z[i] = 1.0e-3 * static_cast<double>((i * 7919) % 1001 - 500);
+    dp[i] = 2.0e-6 * static_cast<double>((i * 104729) % 1001 - 500);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+
+namespace {
+
+int ppl_index(int ppl) {
+  switch (ppl) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    default: return -1;
+  }
+}
+
+using SingleFn = void (*)(BunchDev, int32_t);
+using TilesFn = void (*)(const BunchDev*, const TileDev*, int32_t, int32_t);
+using MixedFn = void (*)(const BunchDev*, const TileDev*);
+
+template <int I, int D>
+constexpr SingleFn single_fn(int pi) {
+  return pi == 0 ? k_track_single<I, D, 1>
+       : pi == 1 ? k_track_single<I, D, 2>
+       : pi == 2 ? k_track_single<I, D, 4>
+                 : k_track_single<I, D, 8>;
+}
+
+template <int I, int D>
+constexpr TilesFn tiles_fn(int pi) {
+  return pi == 0 ? k_track_tiles<I, D, 1>
+       : pi == 1 ? k_track_tiles<I, D, 2>
+       : pi == 2 ? k_track_tiles<I, D, 4>
+                 : k_track_tiles<I, D, 8>;
+}
+
+SingleFn pick_single(int integ, int dtype, int pi) {
+  const bool f = dtype == kF64;
+  switch (integ) {
+    case kEulerCromer: return f ? single_fn<kEulerCromer, kF64>(pi) : single_fn<kEulerCromer, kF32C>(pi);
+    case kLeapfrog: return f ? single_fn<kLeapfrog, kF64>(pi) : single_fn<kLeapfrog, kF32C>(pi);
+    case kRuth4: return f ? single_fn<kRuth4, kF64>(pi) : single_fn<kRuth4, kF32C>(pi);
+    case kRk4: return f ? single_fn<kRk4, kF64>(pi) : single_fn<kRk4, kF32C>(pi);
+    case kMeasureOnly: return f ? single_fn<kMeasureOnly, kF64>(pi) : single_fn<kMeasureOnly, kF32C>(pi);
+    default: return nullptr;
+  }
+}
+
+TilesFn pick_tiles(int integ, int dtype, int pi) {
+  const bool f = dtype == kF64;
+  switch (integ) {
+    case kEulerCromer: return f ? tiles_fn<kEulerCromer, kF64>(pi) : tiles_fn<kEulerCromer, kF32C>(pi);
+    case kLeapfrog: return f ? tiles_fn<kLeapfrog, kF64>(pi) : tiles_fn<kLeapfrog, kF32C>(pi);
+    case kRuth4: return f ? tiles_fn<kRuth4, kF64>(pi) : tiles_fn<kRuth4, kF32C>(pi);
+    case kRk4: return f ? tiles_fn<kRk4, kF64>(pi) : tiles_fn<kRk4, kF32C>(pi);
+    default: return nullptr;
+  }
+}
+
+MixedFn pick_mixed(int pi) {
+  switch (pi) {
+    case 0: return k_track_mixed<1>;
+    case 1: return k_track_mixed<2>;
+    case 2: return k_track_mixed<4>;
+    default: return k_track_mixed<8>;
+  }
+}
+
+size_t lds_bytes(int block, bool moments) {
+  return moments ? static_cast<size_t>(block / kWave) * kLdsDoublesPerWave * sizeof(double) : 0;
+}
+
+}  // namespace
+
+hipError_t launch_track_single(const BunchDev& b, int32_t row0, int ppl, int block,
+                               hipStream_t s) {
+  const int pi = ppl_index(ppl);
+  if (pi < 0 || block % kWave != 0 || block > kMaxBlock || block <= 0) return hipErrorInvalidValue;
+  SingleFn fn = pick_single(b.integrator, b.dtype, pi);
+  if (!fn) return hipErrorInvalidValue;
+  const int wpb = block / kWave;
+  const int64_t blocks = (b.waves + wpb - 1) / wpb;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(block),
+                     lds_bytes(block, b.partials != nullptr), s, b, row0);
+  return hipGetLastError();
+}
+
+hipError_t launch_track_tiles(const BunchDev* bunches, const TileDev* tiles, int64_t ntiles,
+                              int integrator, int dtype, int32_t turns, int32_t row0, int ppl,
+                              int block, bool moments, hipStream_t s) {
+  const int pi = ppl_index(ppl);
+  if (pi < 0 || block % kWave != 0 || block > kMaxBlock || block <= 0) return hipErrorInvalidValue;
+  TilesFn fn = pick_tiles(integrator, dtype, pi);
+  if (!fn) return hipErrorInvalidValue;
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(ntiles)), dim3(block),
+                     lds_bytes(block, moments), s, bunches, tiles, turns, row0);
+  return hipGetLastError();
+}
+
+hipError_t launch_track_mixed(const BunchDev* bunches, const TileDev* tiles, int64_t ntiles,
+                              int ppl, int block, hipStream_t s) {
+  const int pi = ppl_index(ppl);
+  if (pi < 0 || block % kWave != 0 || block > kMaxBlock || block <= 0) return hipErrorInvalidValue;
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pick_mixed(pi), dim3(static_cast<unsigned>(ntiles)), dim3(block),
+                     lds_bytes(block, true), s, bunches, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_single(const FinalizeDev& f, hipStream_t s) {
+  if (f.rows <= 0) return hipSuccess;
+  const int blocks = (f.rows + 3) / 4;
+  hipLaunchKernelGGL(k_finalize_single, dim3(blocks), dim3(256), 0, s, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_multi(const FinalizeDev* fs, int nf, int rows, int64_t out_row0,
+                                 hipStream_t s) {
+  if (nf <= 0 || rows <= 0) return hipSuccess;
+  if (nf > 65535) return hipErrorInvalidValue;
+  const int blocks = (rows + 3) / 4;
+  hipLaunchKernelGGL(k_finalize_multi, dim3(blocks, nf), dim3(256), 0, s, fs, rows, out_row0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_nan(ltrk_moments* out, int64_t rows, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int64_t blocks = (rows + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, out, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_probe(double* z, double* dp, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fill_probe, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, z, dp, n);
+  return hipGetLastError();
+}
+
+}  // namespace ltrk

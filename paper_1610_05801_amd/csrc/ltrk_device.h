@@ -1,0 +1,77 @@
+// Descriptors shared by the HIP kernels and the host runtime of libltrk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ltrk.h"
+
+namespace ltrk {
+
+constexpr int kWave = 64;
+// Turns whose per-lane moment sums are buffered in LDS before one cross-lane
+// reduction ("flush"). Each of the 5 sums of a turn is reduced by 4 lanes
+// holding 16 of the 64 lane values each, so a flush covers 3 turns x 5 sums =
+// 15 rows on 60 lanes.
+constexpr int kFlushTurns = 3;
+constexpr int kLanesPerRow = 4;
+constexpr int kRowStride = 66;  // doubles per LDS row: 64 lane values + 2 pad
+constexpr int kLdsDoublesPerWave = kFlushTurns * 5 * kRowStride;
+constexpr int kMaxBlock = 256;
+
+enum Integrator : int32_t {
+  kEulerCromer = LTRK_EULER_CROMER,
+  kLeapfrog = LTRK_LEAPFROG,
+  kRuth4 = LTRK_RUTH4,
+  kRk4 = LTRK_RK4,
+  kMeasureOnly = 7,  // no turn applied: moments of the current state
+};
+enum DType : int32_t { kF64 = LTRK_F64, kF32C = LTRK_F32C };
+
+// Per-bunch coefficients, derived on the host in FP64 once per call.
+struct Coeffs {
+  double half_rev_per_m;  // s = 2h/C: k z = pi * (s z)
+  double nd[2];           // negated drift weights times D (scheme specific)
+  double kw[2];           // kick weights times A (scheme specific)
+  double neg_D;           // -D (RK4 field)
+  double A;               // A (RK4 field)
+  float nd_f[2];          // nd rounded to FP32, for F32C drift increments
+  float neg_D_f;
+  float pad;
+};
+
+// One bunch as the kernels see it.
+struct BunchDev {
+  void* z;
+  void* dp;
+  void* z_comp;
+  void* dp_comp;
+  int64_t n;
+  int64_t waves;      // ceil(n / (64 * ppl)) wave tiles
+  double* partials;   // [rows][5][waves] per-wave moment sums of this launch's
+                      // first turn row; NULL = no moments
+  Coeffs c;
+  int32_t integrator;
+  int32_t dtype;
+  int32_t turns;      // turns of this launch (engine: min(k, turns left))
+  int32_t active;     // engine: 0 = skip
+};
+
+// A block's unit of work in tiled launches: `waves_per_block` consecutive
+// wave tiles of one bunch starting at wave0.
+struct TileDev {
+  int32_t bunch;
+  int32_t wave0;
+};
+
+// Finalize work: reduce rows of per-wave partial sums of one bunch.
+struct FinalizeDev {
+  const double* partials;
+  int64_t waves;
+  int64_t n;
+  ltrk_moments* out;
+  int32_t rows;
+  int32_t pad;
+};
+
+}  // namespace ltrk

@@ -1,0 +1,887 @@
+// Host runtime and C ABI of libltrk: argument validation, ring constants,
+// per-stream scratch for moment partials, launch sequences (eager, timed or
+// replayed from a cached hipGraph) and the single-bunch / batched tracking
+// entry points declared in include/ltrk.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace ltrk {
+
+// ---------------------------------------------------------------------------
+// Errors
+
+namespace {
+thread_local int t_err_code = 0;
+thread_local char t_err_msg[512] = "";
+}  // namespace
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_err_msg, sizeof(t_err_msg), fmt, ap);
+  va_end(ap);
+  t_err_code = code;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(LTRK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() {
+  t_err_code = 0;
+  t_err_msg[0] = '\0';
+}
+
+// ---------------------------------------------------------------------------
+// Ring constants
+
+bool valid_integrator(int i) { return i >= LTRK_EULER_CROMER && i <= LTRK_RK4; }
+bool valid_dtype(int d) { return d == LTRK_F64 || d == LTRK_F32C; }
+
+int validate_ring(const ltrk_ring* r) {
+  if (!r) return fail(LTRK_EINVAL, "ring is NULL");
+  const double v[7] = {r->circumference_m, r->harmonic, r->voltage_V, r->p0c_eV,
+                       r->mass_eV,         r->gamma_t,  r->charge_e};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(LTRK_EINVAL, "ring parameter is not finite");
+  if (!(r->circumference_m > 0.0)) return fail(LTRK_EINVAL, "circumference must be > 0");
+  if (!(r->harmonic > 0.0) || std::floor(r->harmonic) != r->harmonic)
+    return fail(LTRK_EINVAL, "harmonic must be a positive integer");
+  if (!(r->p0c_eV > 0.0)) return fail(LTRK_EINVAL, "p0c must be > 0");
+  if (!(r->mass_eV >= 0.0)) return fail(LTRK_EINVAL, "mass must be >= 0");
+  if (!(r->gamma_t > 0.0)) return fail(LTRK_EINVAL, "gamma_t must be > 0");
+  return LTRK_OK;
+}
+
+void derive(const ltrk_ring& r, ltrk_derived* o) {
+  // Lorentz factors from the momentum in units of the rest energy.
+  if (r.mass_eV == 0.0) {
+    o->gamma = INFINITY;
+    o->beta = 1.0;
+  } else {
+    const double bg = r.p0c_eV / r.mass_eV;
+    o->gamma = std::sqrt(1.0 + bg * bg);
+    o->beta = bg / o->gamma;
+  }
+  o->eta = 1.0 / (r.gamma_t * r.gamma_t) - 1.0 / (o->gamma * o->gamma);
+  o->kick_amplitude = r.charge_e * r.voltage_V / (o->beta * r.p0c_eV);
+  o->wavenumber = 2.0 * M_PI * r.harmonic / r.circumference_m;
+  o->slip_length = o->eta * r.circumference_m;
+  const double A = o->kick_amplitude, k = o->wavenumber, D = o->slip_length;
+  const double w2 = A * k * D;
+  if (w2 > 0.0) {
+    o->omega_s = std::sqrt(w2);
+    o->q_s = o->omega_s / (2.0 * M_PI);
+    o->q_leapfrog = o->omega_s < 2.0 ? std::asin(0.5 * o->omega_s) / M_PI : NAN;
+    o->bucket_height = 2.0 * std::sqrt(A / (k * D));
+  } else {
+    o->omega_s = o->q_s = o->q_leapfrog = o->bucket_height = NAN;
+  }
+  o->bucket_half_length = 0.5 * r.circumference_m / r.harmonic;
+  o->h_separatrix = -2.0 * A / k;
+}
+
+void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
+  ltrk_derived d;
+  derive(r, &d);
+  const double A = d.kick_amplitude, D = d.slip_length;
+  std::memset(c, 0, sizeof(*c));
+  c->half_rev_per_m = 2.0 * r.harmonic / r.circumference_m;
+  c->neg_D = -D;
+  c->A = A;
+  switch (integrator) {
+    case LTRK_EULER_CROMER:
+      c->nd[0] = -D;
+      c->kw[0] = A;
+      break;
+    case LTRK_LEAPFROG:
+      c->nd[0] = -(0.5 * D);
+      c->kw[0] = A;
+      break;
+    case LTRK_RUTH4: {
+      // Forest-Ruth: drifts th/2, (1-th)/2, (1-th)/2, th/2; kicks th, 1-2th, th.
+      const double th = 1.0 / (2.0 - std::cbrt(2.0));
+      c->nd[0] = -((0.5 * th) * D);
+      c->nd[1] = -((0.5 * (1.0 - th)) * D);
+      c->kw[0] = th * A;
+      c->kw[1] = (1.0 - 2.0 * th) * A;
+      break;
+    }
+    default:
+      break;
+  }
+  c->nd_f[0] = static_cast<float>(c->nd[0]);
+  c->nd_f[1] = static_cast<float>(c->nd[1]);
+  c->neg_D_f = static_cast<float>(c->neg_D);
+}
+
+int64_t waves_for(int64_t n, int ppl) {
+  const int64_t per = static_cast<int64_t>(kWave) * ppl;
+  return (n + per - 1) / per;
+}
+
+int current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  return LTRK_OK;
+}
+
+int check_device_range(const void* p, size_t bytes, const char* name) {
+  if (!p) return fail(LTRK_EINVAL, "%s is NULL", name);
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LTRK_EINVAL, "%s is not device memory", name);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(LTRK_EINVAL, "%s is not device memory", name);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LTRK_EINVAL, "%s: cannot determine its allocation", name);
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || static_cast<size_t>(q - b) + bytes > size)
+    return fail(LTRK_EINVAL, "%s: allocation holds %zu bytes past it, %zu needed", name,
+                size - static_cast<size_t>(q - b), bytes);
+  return LTRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Timing (ltrk_timing_enable)
+
+namespace {
+struct TimedLaunch {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_time_mu;
+bool g_time_on = false;
+std::vector<TimedLaunch> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool timing_on() {
+  std::lock_guard<std::mutex> g(g_time_mu);
+  return g_time_on;
+}
+
+void timing_begin(hipStream_t s, int kind, void** token) {
+  *token = nullptr;
+  std::lock_guard<std::mutex> g(g_time_mu);
+  if (!g_time_on) return;
+  TimedLaunch t{kind, pooled_event(), pooled_event()};
+  if (!t.a || !t.b) return;
+  hipEventRecord(t.a, s);
+  g_timed.push_back(t);
+  *token = reinterpret_cast<void*>(g_timed.size());
+}
+
+void timing_end(hipStream_t s, void* token) {
+  if (!token) return;
+  std::lock_guard<std::mutex> g(g_time_mu);
+  const size_t i = reinterpret_cast<size_t>(token) - 1;
+  if (i < g_timed.size()) hipEventRecord(g_timed[i].b, s);
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequences
+
+namespace {
+
+struct Launch {
+  int kind;  // kTimeTrack / kTimeFinalize
+  std::function<hipError_t(hipStream_t)> fn;
+};
+
+hipError_t run_eager(const std::vector<Launch>& seq, hipStream_t s) {
+  for (const Launch& l : seq) {
+    void* tok = nullptr;
+    timing_begin(s, l.kind, &tok);
+    hipError_t e = l.fn(s);
+    timing_end(s, tok);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> owned;  // device tables that the graph's kernels read
+};
+
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct DeviceCtx {
+  std::mutex mu;
+  std::unordered_map<hipStream_t, Scratch> scratch;
+  std::list<std::pair<std::string, GraphEntry>> graphs;  // most recent first
+  size_t max_graphs = 32;
+};
+
+std::mutex g_ctx_mu;
+std::unordered_map<int, std::unique_ptr<DeviceCtx>> g_ctx;
+
+DeviceCtx& ctx_for(int dev) {
+  std::lock_guard<std::mutex> g(g_ctx_mu);
+  auto& p = g_ctx[dev];
+  if (!p) p.reset(new DeviceCtx);
+  return *p;
+}
+
+size_t scratch_cap_bytes() {
+  static size_t cap = [] {
+    const char* e = std::getenv("LTRK_SCRATCH_MB");
+    long mb = e ? std::atol(e) : 1024;
+    if (mb < 16) mb = 16;
+    return static_cast<size_t>(mb) << 20;
+  }();
+  return cap;
+}
+
+void destroy_entry(GraphEntry& ge) {
+  if (ge.exec) hipGraphExecDestroy(ge.exec);
+  for (void* p : ge.owned) hipFree(p);
+  ge.exec = nullptr;
+  ge.owned.clear();
+}
+
+// Drop every cached graph (device must be idle w.r.t. them).
+void clear_graphs(DeviceCtx& c) {
+  for (auto& kv : c.graphs) destroy_entry(kv.second);
+  c.graphs.clear();
+}
+
+// Scratch of at least `bytes` for stream s (grown, never shrunk).
+int ensure_scratch(DeviceCtx& c, hipStream_t s, size_t bytes, void** out) {
+  Scratch& sc = c.scratch[s];
+  if (sc.bytes >= bytes && sc.ptr) {
+    *out = sc.ptr;
+    return LTRK_OK;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize before scratch growth");
+  clear_graphs(c);  // cached graphs may name the old buffer
+  if (sc.ptr) hipFree(sc.ptr);
+  sc.ptr = nullptr;
+  sc.bytes = 0;
+  size_t want = std::max(bytes, static_cast<size_t>(1) << 20);
+  e = hipMalloc(&sc.ptr, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    sc.ptr = nullptr;
+    return fail(LTRK_ENOMEM, "scratch allocation of %zu bytes failed", want);
+  }
+  sc.bytes = want;
+  *out = sc.ptr;
+  return LTRK_OK;
+}
+
+bool stream_capturing(hipStream_t s) {
+  if (!s) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Run `seq` on s: from the graph cache under `key` when allowed, else eagerly.
+// `owned` device tables are kept alive with the cached graph (or freed after
+// an eager run once the stream is done with them).
+int execute(DeviceCtx& c, const std::string& key, std::vector<Launch>& seq, hipStream_t s,
+            bool use_graph) {
+  const bool graph = use_graph && s != nullptr && !timing_on() && !stream_capturing(s);
+  if (!graph) {
+    hipError_t e = run_eager(seq, s);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return LTRK_OK;
+  }
+  for (auto it = c.graphs.begin(); it != c.graphs.end(); ++it) {
+    if (it->first == key) {
+      c.graphs.splice(c.graphs.begin(), c.graphs, it);
+      hipError_t e = hipGraphLaunch(it->second.exec, s);
+      if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+      return LTRK_OK;
+    }
+  }
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = run_eager(seq, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "kernel launch");
+  }
+  hipError_t le = run_eager(seq, s);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (le != hipSuccess || e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return fail_hip(le != hipSuccess ? le : e, "graph capture");
+  }
+  GraphEntry ge;
+  e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+  if (c.graphs.size() >= c.max_graphs) {
+    hipDeviceSynchronize();
+    destroy_entry(c.graphs.back().second);
+    c.graphs.pop_back();
+  }
+  c.graphs.emplace_front(key, std::move(ge));
+  e = hipGraphLaunch(c.graphs.front().second.exec, s);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  return LTRK_OK;
+}
+
+template <typename T>
+void key_add(std::string& k, const T& v) {
+  k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+// Rows (turns) of partial sums per finalize chunk for `waves_total` waves,
+// a multiple of K unless the whole run is shorter.
+int64_t chunk_rows(int64_t turns, int64_t K, int64_t waves_total) {
+  const int64_t per_row = waves_total * 5 * static_cast<int64_t>(sizeof(double));
+  int64_t cap = static_cast<int64_t>(scratch_cap_bytes()) / std::max<int64_t>(per_row, 1);
+  if (cap >= turns) return turns;
+  if (cap >= K) return (cap / K) * K;
+  return cap;  // may be < K (the caller then shortens launches)
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single-bunch tracking
+
+static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_t turns,
+                        const ltrk_ring* ring, int integrator, int dtype, ltrk_moments* mom,
+                        hipStream_t s) {
+  int rc = validate_ring(ring);
+  if (rc) return rc;
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
+  if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
+  if (turns > INT32_MAX) return fail(LTRK_EINVAL, "turns must be < 2^31");
+  if (turns == 0) return LTRK_OK;
+  if (mom && (rc = check_device_range(mom, static_cast<size_t>(turns) * sizeof(ltrk_moments),
+                                      "moments")))
+    return rc;
+  if (n == 0) {
+    if (!mom) return LTRK_OK;
+    hipError_t e = launch_fill_nan(mom, turns, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "fill moments");
+  }
+  const size_t elem = dtype == LTRK_F64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = static_cast<size_t>(n) * elem;
+  if ((rc = check_device_range(z, bytes, "z"))) return rc;
+  if ((rc = check_device_range(dp, bytes, "dp"))) return rc;
+  if (dtype == LTRK_F32C) {
+    if ((rc = check_device_range(zc, bytes, "z_comp"))) return rc;
+    if ((rc = check_device_range(dc, bytes, "dp_comp"))) return rc;
+  }
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const ltrk_plan plan = choose_plan(integrator, dtype, n, false);
+
+  BunchDev b;
+  std::memset(&b, 0, sizeof(b));
+  b.z = z;
+  b.dp = dp;
+  b.z_comp = zc;
+  b.dp_comp = dc;
+  b.n = n;
+  b.waves = waves_for(n, plan.ppl);
+  b.integrator = integrator;
+  b.dtype = dtype;
+  b.active = 1;
+  make_coeffs(*ring, integrator, &b.c);
+
+  DeviceCtx& c = ctx_for(dev);
+  std::lock_guard<std::mutex> lock(c.mu);
+  int64_t K = plan.turns_per_launch;
+  int64_t rows = turns;
+  void* scratch = nullptr;
+  if (mom) {
+    rows = chunk_rows(turns, K, b.waves);
+    if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)b.waves);
+    K = std::min<int64_t>(K, rows);
+    if ((rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * b.waves * sizeof(double),
+                             &scratch)))
+      return rc;
+  }
+
+  std::string key;
+  key_add(key, 1);
+  key_add(key, b);
+  key_add(key, plan);
+  key_add(key, turns);
+  key_add(key, mom);
+  key_add(key, scratch);
+
+  std::vector<Launch> seq;
+  for (int64_t c0 = 0; c0 < turns; c0 += rows) {
+    const int64_t len = std::min(rows, turns - c0);
+    for (int64_t j = 0; j < len; j += K) {
+      BunchDev bl = b;
+      bl.turns = static_cast<int32_t>(std::min(K, len - j));
+      bl.partials = static_cast<double*>(scratch);
+      const int32_t row0 = static_cast<int32_t>(j);
+      const int ppl = plan.ppl, block = plan.block;
+      seq.push_back({kTimeTrack, [bl, row0, ppl, block](hipStream_t st) {
+                       return launch_track_single(bl, row0, ppl, block, st);
+                     }});
+    }
+    if (mom) {
+      FinalizeDev f;
+      std::memset(&f, 0, sizeof(f));
+      f.partials = static_cast<const double*>(scratch);
+      f.waves = b.waves;
+      f.n = n;
+      f.out = mom + c0;
+      f.rows = static_cast<int32_t>(len);
+      seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+    }
+  }
+  return execute(c, key, seq, s, plan.use_graph != 0);
+}
+
+static int moments_single(const void* z, const void* dp, const void* zc, const void* dc,
+                          int64_t n, int dtype, ltrk_moments* out, hipStream_t s) {
+  int rc;
+  if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
+  if ((rc = check_device_range(out, sizeof(ltrk_moments), "out"))) return rc;
+  if (n == 0) {
+    hipError_t e = launch_fill_nan(out, 1, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "fill moments");
+  }
+  const size_t bytes = static_cast<size_t>(n) * (dtype == LTRK_F64 ? 8 : 4);
+  if ((rc = check_device_range(z, bytes, "z"))) return rc;
+  if ((rc = check_device_range(dp, bytes, "dp"))) return rc;
+  if (dtype == LTRK_F32C) {
+    if ((rc = check_device_range(zc, bytes, "z_comp"))) return rc;
+    if ((rc = check_device_range(dc, bytes, "dp_comp"))) return rc;
+  }
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const int ppl = 4, block = 256;
+  BunchDev b;
+  std::memset(&b, 0, sizeof(b));
+  b.z = const_cast<void*>(z);
+  b.dp = const_cast<void*>(dp);
+  b.z_comp = const_cast<void*>(zc);
+  b.dp_comp = const_cast<void*>(dc);
+  b.n = n;
+  b.waves = waves_for(n, ppl);
+  b.integrator = kMeasureOnly;
+  b.dtype = dtype;
+  b.turns = 1;
+  b.active = 1;
+  DeviceCtx& c = ctx_for(dev);
+  std::lock_guard<std::mutex> lock(c.mu);
+  void* scratch = nullptr;
+  if ((rc = ensure_scratch(c, s, static_cast<size_t>(5) * b.waves * sizeof(double), &scratch)))
+    return rc;
+  b.partials = static_cast<double*>(scratch);
+  hipError_t e = launch_track_single(b, 0, ppl, block, s);
+  if (e != hipSuccess) return fail_hip(e, "moments launch");
+  FinalizeDev f;
+  std::memset(&f, 0, sizeof(f));
+  f.partials = b.partials;
+  f.waves = b.waves;
+  f.n = n;
+  f.out = out;
+  f.rows = 1;
+  e = launch_finalize_single(f, s);
+  return e == hipSuccess ? LTRK_OK : fail_hip(e, "moments finalize");
+}
+
+// ---------------------------------------------------------------------------
+// Batched tracking
+
+static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int integrator,
+                         int dtype, hipStream_t s) {
+  int rc;
+  if (nb < 0 || (nb > 0 && !bunches)) return fail(LTRK_EINVAL, "invalid bunch table");
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (!valid_dtype(dtype)) return fail(LTRK_EINVAL, "unknown dtype %d", dtype);
+  if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
+  if (turns > INT32_MAX) return fail(LTRK_EINVAL, "turns must be < 2^31");
+  if (nb > 65535) return fail(LTRK_EINVAL, "at most 65535 bunches per call");
+  const size_t elem = dtype == LTRK_F64 ? 8 : 4;
+  int64_t total_n = 0;
+  for (int i = 0; i < nb; ++i) {
+    const ltrk_bunch& b = bunches[i];
+    if (b.n < 0) return fail(LTRK_EINVAL, "bunch %d: n < 0", i);
+    if ((rc = validate_ring(&b.ring))) return fail(rc, "bunch %d: invalid ring", i);
+    if (turns > 0 && b.moments &&
+        (rc = check_device_range(b.moments, static_cast<size_t>(turns) * sizeof(ltrk_moments),
+                                 "bunch moments")))
+      return rc;
+    if (b.n > 0 && turns > 0) {
+      const size_t bytes = static_cast<size_t>(b.n) * elem;
+      if ((rc = check_device_range(b.z, bytes, "bunch z"))) return rc;
+      if ((rc = check_device_range(b.dp, bytes, "bunch dp"))) return rc;
+      if (dtype == LTRK_F32C) {
+        if ((rc = check_device_range(b.z_comp, bytes, "bunch z_comp"))) return rc;
+        if ((rc = check_device_range(b.dp_comp, bytes, "bunch dp_comp"))) return rc;
+      }
+    }
+    total_n += b.n;
+  }
+  if (turns == 0 || nb == 0) return LTRK_OK;
+  for (int i = 0; i < nb; ++i) {
+    if (bunches[i].n == 0 && bunches[i].moments) {
+      hipError_t e = launch_fill_nan(bunches[i].moments, turns, s);
+      if (e != hipSuccess) return fail_hip(e, "fill moments");
+    }
+  }
+  if (total_n == 0) return LTRK_OK;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const ltrk_plan plan = choose_plan(integrator, dtype, total_n, true);
+  const int wpb = plan.block / kWave;
+
+  std::vector<BunchDev> bd(nb);
+  std::vector<TileDev> tiles;
+  int64_t waves_mom = 0;  // waves of bunches that want moments
+  bool any_mom = false;
+  for (int i = 0; i < nb; ++i) {
+    const ltrk_bunch& in = bunches[i];
+    BunchDev& b = bd[i];
+    std::memset(&b, 0, sizeof(b));
+    b.z = in.z;
+    b.dp = in.dp;
+    b.z_comp = in.z_comp;
+    b.dp_comp = in.dp_comp;
+    b.n = in.n;
+    b.waves = waves_for(in.n, plan.ppl);
+    b.integrator = integrator;
+    b.dtype = dtype;
+    b.active = 1;
+    make_coeffs(in.ring, integrator, &b.c);
+    for (int64_t w0 = 0; w0 < b.waves; w0 += wpb) {
+      if (w0 > INT32_MAX) return fail(LTRK_EINVAL, "bunch %d too large", i);
+      tiles.push_back(TileDev{i, static_cast<int32_t>(w0)});
+    }
+    if (in.moments && in.n > 0) {
+      waves_mom += b.waves;
+      any_mom = true;
+    }
+  }
+  int64_t K = plan.turns_per_launch;
+  int64_t rows = turns;
+  if (any_mom) {
+    rows = chunk_rows(turns, K, waves_mom);
+    if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)waves_mom);
+    K = std::min<int64_t>(K, rows);
+  }
+
+  DeviceCtx& c = ctx_for(dev);
+  std::lock_guard<std::mutex> lock(c.mu);
+  void* scratch = nullptr;
+  if (any_mom &&
+      (rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * waves_mom * sizeof(double),
+                           &scratch)))
+    return rc;
+  // Per-bunch partial regions inside the scratch.
+  std::vector<FinalizeDev> fin;
+  int64_t off = 0;
+  int max_rows = static_cast<int>(std::min<int64_t>(rows, turns));
+  for (int i = 0; i < nb; ++i) {
+    if (bunches[i].moments && bunches[i].n > 0) {
+      bd[i].partials = static_cast<double*>(scratch) + off;
+      FinalizeDev f;
+      std::memset(&f, 0, sizeof(f));
+      f.partials = bd[i].partials;
+      f.waves = bd[i].waves;
+      f.n = bd[i].n;
+      f.out = bunches[i].moments;
+      f.rows = max_rows;
+      fin.push_back(f);
+      off += rows * 5 * bd[i].waves;
+    }
+  }
+
+  std::string key;
+  key_add(key, 2);
+  key_add(key, plan);
+  key_add(key, turns);
+  key_add(key, scratch);
+  key.append(reinterpret_cast<const char*>(bd.data()), bd.size() * sizeof(BunchDev));
+  for (const FinalizeDev& f : fin) key_add(key, f.out);
+
+  // Device tables: found with a cached graph, else uploaded now.
+  const bool graph_ok = plan.use_graph && s && !timing_on() && !stream_capturing(s);
+  if (graph_ok) {
+    for (auto it = c.graphs.begin(); it != c.graphs.end(); ++it) {
+      if (it->first == key) {
+        c.graphs.splice(c.graphs.begin(), c.graphs, it);
+        hipError_t e = hipGraphLaunch(it->second.exec, s);
+        return e == hipSuccess ? LTRK_OK : fail_hip(e, "hipGraphLaunch");
+      }
+    }
+  }
+  const size_t tb_bytes = bd.size() * sizeof(BunchDev);
+  const size_t tt_bytes = tiles.size() * sizeof(TileDev);
+  const size_t tf_bytes = std::max<size_t>(fin.size(), 1) * sizeof(FinalizeDev);
+  void* tables = nullptr;
+  hipError_t e = hipMalloc(&tables, tb_bytes + tt_bytes + tf_bytes + 512);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LTRK_ENOMEM, "bunch tables");
+  }
+  char* base = static_cast<char*>(tables);
+  BunchDev* d_b = reinterpret_cast<BunchDev*>(base);
+  TileDev* d_t = reinterpret_cast<TileDev*>(base + ((tb_bytes + 255) & ~size_t(255)));
+  FinalizeDev* d_f = reinterpret_cast<FinalizeDev*>(
+      reinterpret_cast<char*>(d_t) + ((tt_bytes + 255) & ~size_t(255)));
+  // Synchronous upload: the tables are then fixed for the life of the graph.
+  if ((e = hipMemcpy(d_b, bd.data(), tb_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_t, tiles.data(), tt_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+      (!fin.empty() &&
+       (e = hipMemcpy(d_f, fin.data(), fin.size() * sizeof(FinalizeDev), hipMemcpyHostToDevice)) !=
+           hipSuccess)) {
+    hipFree(tables);
+    return fail_hip(e, "upload bunch tables");
+  }
+
+  std::vector<Launch> seq;
+  const int64_t ntiles = static_cast<int64_t>(tiles.size());
+  const int nf = static_cast<int>(fin.size());
+  for (int64_t c0 = 0; c0 < turns; c0 += rows) {
+    const int64_t len = std::min(rows, turns - c0);
+    for (int64_t j = 0; j < len; j += K) {
+      const int32_t tk = static_cast<int32_t>(std::min(K, len - j));
+      const int32_t row0 = static_cast<int32_t>(j);
+      const ltrk_plan p = plan;
+      const bool m = any_mom;
+      seq.push_back({kTimeTrack, [=](hipStream_t st) {
+                       return launch_track_tiles(d_b, d_t, ntiles, integrator, dtype, tk, row0,
+                                                 p.ppl, p.block, m, st);
+                     }});
+    }
+    if (nf > 0) {
+      const int mr = static_cast<int>(len);
+      seq.push_back({kTimeFinalize, [=](hipStream_t st) {
+                       return launch_finalize_multi(d_f, nf, mr, c0, st);
+                     }});
+    }
+  }
+  if (!graph_ok) {
+    e = run_eager(seq, s);
+    // tables are freed once the stream has consumed them
+    hipError_t se = hipStreamSynchronize(s);
+    hipFree(tables);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    if (se != hipSuccess) return fail_hip(se, "batched run");
+    return LTRK_OK;
+  }
+  rc = execute(c, key, seq, s, true);
+  if (rc) {
+    hipStreamSynchronize(s);
+    hipFree(tables);
+    return rc;
+  }
+  c.graphs.front().second.owned.push_back(tables);
+  return LTRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Shutdown
+
+static int shutdown_all() {
+  std::lock_guard<std::mutex> g(g_ctx_mu);
+  int prev = 0;
+  hipGetDevice(&prev);
+  for (auto& kv : g_ctx) {
+    hipSetDevice(kv.first);
+    hipDeviceSynchronize();
+    DeviceCtx& c = *kv.second;
+    std::lock_guard<std::mutex> lock(c.mu);
+    clear_graphs(c);
+    for (auto& sc : c.scratch)
+      if (sc.second.ptr) hipFree(sc.second.ptr);
+    c.scratch.clear();
+  }
+  g_ctx.clear();
+  hipSetDevice(prev);
+  std::lock_guard<std::mutex> t(g_time_mu);
+  for (auto& tl : g_timed) {
+    hipEventDestroy(tl.a);
+    hipEventDestroy(tl.b);
+  }
+  g_timed.clear();
+  for (hipEvent_t e : g_event_pool) hipEventDestroy(e);
+  g_event_pool.clear();
+  return LTRK_OK;
+}
+
+static int timing_take(ltrk_timing* out) {
+  std::lock_guard<std::mutex> g(g_time_mu);
+  ltrk_timing r{0, 0.0, 0, 0.0};
+  int rc = LTRK_OK;
+  for (auto& tl : g_timed) {
+    hipError_t e = hipEventSynchronize(tl.b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, tl.a, tl.b);
+    if (e != hipSuccess && rc == LTRK_OK) rc = fail_hip(e, "timing events");
+    if (tl.kind == kTimeTrack) {
+      r.track_launches++;
+      r.track_ms += ms;
+    } else {
+      r.finalize_launches++;
+      r.finalize_ms += ms;
+    }
+    g_event_pool.push_back(tl.a);
+    g_event_pool.push_back(tl.b);
+  }
+  g_timed.clear();
+  if (out) *out = r;
+  return rc;
+}
+
+}  // namespace ltrk
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+using namespace ltrk;
+
+#define LTRK_GUARD(body)                                      \
+  try {                                                       \
+    clear_error();                                            \
+    body                                                      \
+  } catch (const std::bad_alloc&) {                           \
+    return fail(LTRK_ENOMEM, "host allocation failed");       \
+  } catch (...) {                                             \
+    return fail(LTRK_EDEVICE, "unexpected internal error");   \
+  }
+
+extern "C" {
+
+int ltrk_abi_version(void) { return LTRK_ABI_VERSION; }
+
+int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out) {
+  LTRK_GUARD({
+    int rc = validate_ring(ring);
+    if (rc) return rc;
+    if (!out) return fail(LTRK_EINVAL, "out is NULL");
+    derive(*ring, out);
+    return LTRK_OK;
+  })
+}
+
+int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_ring* ring,
+                   int integrator, ltrk_moments* moments, void* stream) {
+  LTRK_GUARD({
+    return track_single(z, dp, nullptr, nullptr, n, turns, ring, integrator, LTRK_F64, moments,
+                        static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_track_f32c(float* z, float* dp, float* z_comp, float* dp_comp, int64_t n,
+                    int64_t turns, const ltrk_ring* ring, int integrator, ltrk_moments* moments,
+                    void* stream) {
+  LTRK_GUARD({
+    return track_single(z, dp, z_comp, dp_comp, n, turns, ring, integrator, LTRK_F32C, moments,
+                        static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_moments_f64(const double* z, const double* dp, int64_t n, ltrk_moments* out,
+                     void* stream) {
+  LTRK_GUARD({
+    return moments_single(z, dp, nullptr, nullptr, n, LTRK_F64, out,
+                          static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_moments_f32c(const float* z, const float* dp, const float* z_comp,
+                      const float* dp_comp, int64_t n, ltrk_moments* out, void* stream) {
+  LTRK_GUARD({
+    return moments_single(z, dp, z_comp, dp_comp, n, LTRK_F32C, out,
+                          static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int integrator,
+                       int dtype, void* stream) {
+  LTRK_GUARD({
+    return track_batched(bunches, nb, turns, integrator, dtype, static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_timing_enable(int on) {
+  LTRK_GUARD({
+    std::lock_guard<std::mutex> g(g_time_mu);
+    g_time_on = on != 0;
+    return LTRK_OK;
+  })
+}
+
+int ltrk_timing_take(ltrk_timing* out) {
+  LTRK_GUARD({ return timing_take(out); })
+}
+
+const char* ltrk_strerror(int code) {
+  switch (code) {
+    case LTRK_OK: return "success";
+    case LTRK_EINVAL: return "invalid argument";
+    case LTRK_ENOMEM: return "out of memory";
+    case LTRK_EDEVICE: return "device (HIP) error";
+    case LTRK_EAGAIN: return "resource temporarily unavailable";
+    case LTRK_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error code";
+  }
+}
+
+int ltrk_last_error(char* buf, size_t len) {
+  if (buf && len > 0) {
+    std::strncpy(buf, t_err_msg, len - 1);
+    buf[len - 1] = '\0';
+  }
+  return t_err_code;
+}
+
+int ltrk_shutdown(void) {
+  LTRK_GUARD({ return shutdown_all(); })
+}
+
+}  // extern "C"

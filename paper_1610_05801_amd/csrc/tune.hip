@@ -1,0 +1,311 @@
+// Launch plans for libltrk: a process-wide forced plan, a tuning cache filled
+// by the project's own autotuner (times candidate plans on scratch particles
+// with HIP events), and a built-in default.
+//
+// A plan is (K turns per launch, block size, particles per lane P, graph
+// replay). P changes the order of the moment sums (lane-local over P
+// particles), so results are bit-identical across plans with the same P and
+// agree to rounding across different P.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+extern "C" int ltrk_track_f64(double*, double*, int64_t, int64_t, const ltrk_ring*, int,
+                              ltrk_moments*, void*);
+extern "C" int ltrk_track_f32c(float*, float*, float*, float*, int64_t, int64_t,
+                               const ltrk_ring*, int, ltrk_moments*, void*);
+
+namespace ltrk {
+
+namespace {
+
+using TuneKey = std::tuple<std::string, int, int, int, int>;  // arch, integ, dtype, log2 n, batched
+
+std::mutex g_plan_mu;
+bool g_forced = false;
+ltrk_plan g_forced_plan{128, 256, 4, 1};
+std::map<TuneKey, ltrk_plan> g_tuned;
+
+bool plan_valid(const ltrk_plan& p) {
+  const bool k_ok = p.turns_per_launch >= 1 && p.turns_per_launch <= 65536;
+  const bool b_ok = p.block == 64 || p.block == 128 || p.block == 256;
+  const bool p_ok = p.ppl == 1 || p.ppl == 2 || p.ppl == 4 || p.ppl == 8;
+  return k_ok && b_ok && p_ok && (p.use_graph == 0 || p.use_graph == 1);
+}
+
+std::string device_arch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string a(prop.gcnArchName);
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int log2_bucket(int64_t n) {
+  int b = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+}  // namespace
+
+ltrk_plan default_plan(int /*integrator*/, int /*dtype*/, int64_t n, bool /*batched*/) {
+  ltrk_plan p;
+  p.turns_per_launch = 128;
+  p.block = 256;
+  p.use_graph = 1;
+  // Enough wave tiles to give every one of the 1024 SIMDs work: prefer more
+  // particles per lane (ILP, cheaper moment reduction) only when that still
+  // leaves >= 2 waves per SIMD.
+  if (waves_for(n, 4) >= 2048)
+    p.ppl = 4;
+  else if (waves_for(n, 2) >= 2048)
+    p.ppl = 2;
+  else
+    p.ppl = 1;
+  if (waves_for(n, p.ppl) < 1024) p.block = 64;
+  return p;
+}
+
+ltrk_plan choose_plan(int integrator, int dtype, int64_t n, bool batched) {
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  if (g_forced) return g_forced_plan;
+  auto it = g_tuned.find(TuneKey(device_arch(), integrator, dtype, log2_bucket(n), batched));
+  if (it != g_tuned.end()) return it->second;
+  return default_plan(integrator, dtype, n, batched);
+}
+
+namespace {
+
+// Time one single-bunch call with plan p; returns milliseconds or < 0.
+double time_call(int integrator, int dtype, int64_t n, int64_t turns, void* const* arrays,
+                 ltrk_moments* mom, hipStream_t s, const ltrk_ring& ring, const ltrk_plan& p,
+                 int* rc_out) {
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_forced = true;
+    g_forced_plan = p;
+  }
+  auto call = [&]() {
+    if (dtype == LTRK_F64)
+      return ltrk_track_f64(static_cast<double*>(arrays[0]), static_cast<double*>(arrays[1]), n,
+                            turns, &ring, integrator, mom, s);
+    return ltrk_track_f32c(static_cast<float*>(arrays[0]), static_cast<float*>(arrays[1]),
+                           static_cast<float*>(arrays[2]), static_cast<float*>(arrays[3]), n,
+                           turns, &ring, integrator, mom, s);
+  };
+  double best = -1.0;
+  int rc = call();  // warm-up (and graph capture)
+  hipEvent_t a = nullptr, b = nullptr;
+  if (rc == LTRK_OK && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    for (int rep = 0; rep < 2 && rc == LTRK_OK; ++rep) {
+      hipEventRecord(a, s);
+      rc = call();
+      hipEventRecord(b, s);
+      if (hipEventSynchronize(b) != hipSuccess) {
+        rc = fail(LTRK_EDEVICE, "autotune: event synchronisation failed");
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, a, b);
+      if (rc == LTRK_OK && (best < 0.0 || ms < best)) best = ms;
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  *rc_out = rc;
+  return rc == LTRK_OK ? best : -1.0;
+}
+
+int autotune(int integrator, int dtype, int64_t n, hipStream_t s, ltrk_plan* best_out) {
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (!valid_dtype(dtype)) return fail(LTRK_EINVAL, "unknown dtype %d", dtype);
+  if (n < 1 || n > (int64_t(1) << 34)) return fail(LTRK_EINVAL, "n out of range for tuning");
+  // Work per probe call ~2^29 particle-turns (a few ms at full rate).
+  int64_t turns = (int64_t(1) << 29) / n;
+  turns = turns < 64 ? 64 : (turns > 4096 ? 4096 : turns);
+  const size_t elem = dtype == LTRK_F64 ? 8 : 4;
+  const int narr = dtype == LTRK_F64 ? 2 : 4;
+  void* arrays[4] = {nullptr, nullptr, nullptr, nullptr};
+  ltrk_moments* mom = nullptr;
+  int rc = LTRK_OK;
+  for (int i = 0; i < narr && rc == LTRK_OK; ++i)
+    if (hipMalloc(&arrays[i], static_cast<size_t>(n) * elem) != hipSuccess)
+      rc = fail(LTRK_ENOMEM, "autotune state");
+  if (rc == LTRK_OK &&
+      hipMalloc(reinterpret_cast<void**>(&mom), static_cast<size_t>(4096) * sizeof(ltrk_moments)) !=
+          hipSuccess)
+    rc = fail(LTRK_ENOMEM, "autotune moments");
+  if (rc == LTRK_OK) {
+    if (dtype == LTRK_F64) {
+      hipError_t e = launch_fill_probe(static_cast<double*>(arrays[0]),
+                                       static_cast<double*>(arrays[1]), n, s);
+      if (e != hipSuccess) rc = fail_hip(e, "autotune fill");
+    } else {
+      for (int i = 0; i < 4; ++i) hipMemsetAsync(arrays[i], 0, static_cast<size_t>(n) * elem, s);
+    }
+  }
+  // Ring of the plain workload: 6911 m, h 4620, 2 MV, 26 GeV/c protons.
+  const ltrk_ring ring{6911.0, 4620.0, 2.0e6, 26.0e9, 0.938e9, 22.77, 1.0};
+  bool saved_forced;
+  ltrk_plan saved_plan;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    saved_forced = g_forced;
+    saved_plan = g_forced_plan;
+  }
+  ltrk_plan best{128, 256, 4, 1};
+  double best_rate = -1.0;
+  const int ppls[4] = {1, 2, 4, 8};
+  const int blocks[3] = {64, 128, 256};
+  for (int pi = 0; pi < 4 && rc == LTRK_OK; ++pi) {
+    for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
+      ltrk_plan p{128, blocks[bi], ppls[pi], 1};
+      const double ms = time_call(integrator, dtype, n, turns, arrays, mom, s, ring, p, &rc);
+      if (ms > 0.0) {
+        const double rate = static_cast<double>(n) * turns / ms;
+        if (rate > best_rate) {
+          best_rate = rate;
+          best = p;
+        }
+      }
+    }
+  }
+  const int ks[6] = {16, 32, 64, 128, 256, 512};
+  for (int ki = 0; ki < 6 && rc == LTRK_OK; ++ki) {
+    ltrk_plan p = best;
+    p.turns_per_launch = ks[ki];
+    const int64_t t = turns < 2 * ks[ki] ? 2 * ks[ki] : turns;
+    const double ms = time_call(integrator, dtype, n, t > 4096 ? 4096 : t, arrays, mom, s, ring, p, &rc);
+    if (ms > 0.0) {
+      const double rate = static_cast<double>(n) * (t > 4096 ? 4096 : t) / ms;
+      if (rate > best_rate * 1.01) {
+        best_rate = rate;
+        best = p;
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_forced = saved_forced;
+    g_forced_plan = saved_plan;
+  }
+  hipStreamSynchronize(s);
+  for (void* p : arrays)
+    if (p) hipFree(p);
+  if (mom) hipFree(mom);
+  if (rc != LTRK_OK) return rc;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_tuned[TuneKey(device_arch(), integrator, dtype, log2_bucket(n), 0)] = best;
+    g_tuned[TuneKey(device_arch(), integrator, dtype, log2_bucket(n), 1)] = best;
+  }
+  if (best_out) *best_out = best;
+  return LTRK_OK;
+}
+
+}  // namespace
+}  // namespace ltrk
+
+using namespace ltrk;
+
+extern "C" {
+
+int ltrk_set_plan(const ltrk_plan* plan) {
+  clear_error();
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  if (!plan) {
+    g_forced = false;
+    return LTRK_OK;
+  }
+  if (!plan_valid(*plan))
+    return fail(LTRK_EINVAL, "invalid plan (K %d, block %d, ppl %d, graph %d)",
+                plan->turns_per_launch, plan->block, plan->ppl, plan->use_graph);
+  g_forced = true;
+  g_forced_plan = *plan;
+  return LTRK_OK;
+}
+
+int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out) {
+  clear_error();
+  if (!out) return fail(LTRK_EINVAL, "out is NULL");
+  if (!valid_integrator(integrator) || !valid_dtype(dtype) || n < 0)
+    return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
+  *out = choose_plan(integrator, dtype, n, false);
+  return LTRK_OK;
+}
+
+int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best) {
+  try {
+    clear_error();
+    return autotune(integrator, dtype, n, static_cast<hipStream_t>(stream), best);
+  } catch (...) {
+    return fail(LTRK_EDEVICE, "unexpected internal error in autotune");
+  }
+}
+
+int ltrk_tune_cache_save(const char* path) {
+  clear_error();
+  if (!path) return fail(LTRK_EINVAL, "path is NULL");
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(LTRK_EINVAL, "cannot open %s", path);
+  std::fprintf(f, "# arch integrator dtype log2n batched K block ppl graph\n");
+  for (const auto& kv : g_tuned) {
+    const auto& k = kv.first;
+    const ltrk_plan& p = kv.second;
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k),
+                 std::get<2>(k), std::get<3>(k), std::get<4>(k), p.turns_per_launch, p.block, p.ppl,
+                 p.use_graph);
+  }
+  std::fclose(f);
+  return LTRK_OK;
+}
+
+int ltrk_tune_cache_load(const char* path) {
+  clear_error();
+  if (!path) return fail(LTRK_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(LTRK_EINVAL, "cannot open %s", path);
+  char line[256];
+  int loaded = 0;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    char arch[64];
+    int integ, dtype, bucket, batched;
+    ltrk_plan p;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d", arch, &integ, &dtype, &bucket, &batched,
+                    &p.turns_per_launch, &p.block, &p.ppl, &p.use_graph) == 9 &&
+        plan_valid(p) && valid_integrator(integ) && valid_dtype(dtype)) {
+      g_tuned[TuneKey(arch, integ, dtype, bucket, batched)] = p;
+      ++loaded;
+    }
+  }
+  std::fclose(f);
+  return loaded >= 0 ? LTRK_OK : LTRK_EINVAL;
+}
+
+}  // extern "C"

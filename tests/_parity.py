@@ -1,0 +1,39 @@
+"""Shared helpers for GPU-vs-oracle comparisons.
+
+Per-particle error norm (the per-coordinate relative error is undefined at
+zero crossings): coordinates are scaled by the bucket half-length z_b = C/(2h)
+and half-height dp_b, and
+    e = |(dz/z_b, ddp/dp_b)| / |(z/z_b, dp/dp_b)|.
+Particles whose initial Hamiltonian lies within 1% of the separatrix value are
+"near-separatrix": there the map is chaotic and last-bit differences grow, so
+they get a looser bound and are counted separately.
+"""
+import numpy as np
+
+import oracle
+
+
+def bucket_error(z, dp, z_ref, dp_ref, ring):
+    c = oracle.derive(ring)
+    zb, db = c["bucket_half_length"], c["bucket_height"]
+    num = np.hypot((np.asarray(z) - z_ref) / zb, (np.asarray(dp) - dp_ref) / db)
+    den = np.hypot(z_ref / zb, dp_ref / db)
+    return num / np.maximum(den, 1e-300)
+
+
+def near_separatrix(z0, dp0, ring, width=0.01):
+    c = oracle.derive(ring)
+    h = oracle.hamiltonian(z0, dp0, ring)
+    return np.abs(h - c["H_sep"]) / abs(c["H_sep"]) <= width
+
+
+def moment_error(m_gpu, m_ref):
+    """Per-row relative error of the 5 moments; means are scaled by the rms."""
+    m_gpu = np.asarray(m_gpu)
+    m_ref = np.asarray(m_ref)
+    err = np.empty_like(m_ref)
+    err[:, 0] = np.abs(m_gpu[:, 0] - m_ref[:, 0]) / m_ref[:, 1]
+    err[:, 2] = np.abs(m_gpu[:, 2] - m_ref[:, 2]) / m_ref[:, 3]
+    for j in (1, 3, 4):
+        err[:, j] = np.abs(m_gpu[:, j] - m_ref[:, j]) / np.abs(m_ref[:, j])
+    return err

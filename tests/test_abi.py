@@ -1,0 +1,129 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+that include/ltrk.h declares, and its host-only logic (constant derivation,
+argument validation, error strings, plans) behaves as documented. No kernel
+is launched here."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ltrk.h")
+
+ltrk = pytest.importorskip("paper_1610_05801_amd")
+
+import oracle  # noqa: E402
+from synth import SPS_RING  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ltrk_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declarations_are_exported():
+    names = declared_functions()
+    assert len(names) >= 25
+    out = subprocess.run(["nm", "-D", "--defined-only", ltrk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (ltrk_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(ltrk.LIB_PATH)
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_binding_covers_header():
+    assert set(declared_functions()) == set(ltrk.EXPORTED)
+
+
+def test_abi_version():
+    assert ltrk.ltrk_abi_version() == 1
+
+
+def test_derive_matches_oracle():
+    d = ltrk.ltrk_derive(SPS_RING)
+    o = oracle.derive(SPS_RING)
+    pairs = [("gamma", "gamma"), ("beta", "beta"), ("eta", "eta"), ("kick_amplitude", "A"),
+             ("wavenumber", "k"), ("slip_length", "D"), ("omega_s", "omega"), ("q_s", "Qs"),
+             ("q_leapfrog", "Q_lf"), ("bucket_half_length", "bucket_half_length"),
+             ("bucket_height", "bucket_height"), ("h_separatrix", "H_sep")]
+    for a, b in pairs:
+        assert abs(d[a] - o[b]) <= 1e-14 * abs(o[b]), (a, d[a], o[b])
+
+
+def test_derive_unstable_ring_has_nan_tune():
+    d = ltrk.ltrk_derive(dict(SPS_RING, gamma_t=40.0))
+    assert d["eta"] < 0 and math.isnan(d["q_s"]) and math.isnan(d["bucket_height"])
+
+
+@pytest.mark.parametrize("key,val", [("circumference_m", 0.0), ("harmonic", 0.0),
+                                     ("harmonic", 4620.5), ("p0c_eV", -1.0),
+                                     ("mass_eV", -1.0), ("gamma_t", 0.0),
+                                     ("voltage_V", float("inf"))])
+def test_invalid_ring_rejected(key, val):
+    with pytest.raises(ltrk.LtrkError) as e:
+        ltrk.ltrk_derive(dict(SPS_RING, **{key: val}))
+    assert e.value.code == ltrk.LTRK_EINVAL
+
+
+def _raw():
+    return ctypes.CDLL(ltrk.LIB_PATH)
+
+
+def test_track_rejects_invalid_arguments_before_any_launch():
+    lib = _raw()
+    r = ltrk.Ring.of(SPS_RING)
+    f = lib.ltrk_track_f64
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.POINTER(ltrk.Ring), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    # negative sizes, unknown scheme, NULL arrays with n > 0, host memory
+    assert f(None, None, -1, 10, ctypes.byref(r), 1, None, None) == ltrk.LTRK_EINVAL
+    assert f(None, None, 10, -1, ctypes.byref(r), 1, None, None) == ltrk.LTRK_EINVAL
+    assert f(None, None, 10, 10, ctypes.byref(r), 9, None, None) == ltrk.LTRK_EINVAL
+    assert f(None, None, 10, 10, None, 1, None, None) == ltrk.LTRK_EINVAL
+    host = (ctypes.c_double * 10)()
+    rc = f(host, host, 10, 10, ctypes.byref(r), 1, None, None)
+    assert rc == ltrk.LTRK_EINVAL
+    code, msg = ltrk.ltrk_last_error()
+    assert code == ltrk.LTRK_EINVAL and "device memory" in msg
+    # n = 0 or turns = 0 without moments: success, nothing enqueued
+    assert f(None, None, 0, 10, ctypes.byref(r), 1, None, None) == 0
+    assert f(None, None, 10, 0, ctypes.byref(r), 1, None, None) == 0
+
+
+def test_batched_rejects_bad_tables():
+    lib = _raw()
+    f = lib.ltrk_track_batched
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_void_p]
+    assert f(None, 3, 10, 1, 0, None) == ltrk.LTRK_EINVAL
+    arr = (ltrk._binding.Bunch * 1)()
+    arr[0].n = -5
+    arr[0].ring = ltrk.Ring.of(SPS_RING)
+    assert f(ctypes.cast(arr, ctypes.c_void_p), 1, 10, 1, 0, None) == ltrk.LTRK_EINVAL
+    arr[0].n = 4
+    assert f(ctypes.cast(arr, ctypes.c_void_p), 1, 10, 1, 7, None) == ltrk.LTRK_EINVAL
+
+
+def test_strerror_and_plans():
+    assert ltrk.ltrk_strerror(0) == "success"
+    assert "invalid" in ltrk.ltrk_strerror(-1)
+    p = ltrk.ltrk_get_plan("leapfrog", "f64", 1_000_000)
+    assert p["ppl"] in (1, 2, 4, 8) and p["block"] in (64, 128, 256)
+    ltrk.ltrk_set_plan(64, 128, 2, 0)
+    assert ltrk.ltrk_get_plan("ruth4", "f32c", 10) == {"turns_per_launch": 64, "block": 128,
+                                                       "ppl": 2, "use_graph": 0}
+    with pytest.raises(ltrk.LtrkError):
+        ltrk.ltrk_set_plan(64, 96, 2, 0)
+    ltrk.ltrk_set_plan()
+    assert ltrk.ltrk_get_plan("leapfrog", "f64", 1_000_000) == p
+
+
+def test_engine_footprint():
+    assert ltrk.ltrk_engine_footprint(1000, 100) == 16128 + 4096
+    assert ltrk.ltrk_engine_footprint(10_000_000, 100_000) == 160_000_000 + 4_000_000

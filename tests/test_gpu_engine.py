@@ -1,0 +1,121 @@
+"""Serving engine: jobs of different sizes, schemes and precisions admitted
+while others run, advanced together step by step; each job's result is
+bitwise equal to tracking it alone with the same particles-per-lane (4), and
+admission respects slots and the arena budget."""
+import numpy as np
+import pytest
+
+from synth import SPS_RING, gaussian_bunch, split_f32c
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ltrk():
+    import paper_1610_05801_amd as m
+    yield m
+    m.ltrk_set_plan()
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+JOBS = [(1000, 250, "leapfrog", "f64"), (70_001, 90, "ruth4", "f32c"),
+        (5, 400, "euler_cromer", "f64"), (30_000, 333, "rk4", "f64"),
+        (4097, 120, "leapfrog", "f32c")]
+
+
+def alone(ltrk, n, turns, integ, dtype, z0, dp0):
+    ltrk.ltrk_set_plan(128, 256, 4, 0)
+    mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda")
+    if dtype == "f64":
+        z, dp = dev(z0, torch.float64), dev(dp0, torch.float64)
+        ltrk.ltrk_track_f64(z, dp, turns, SPS_RING, integ, mom)
+        out = [z, dp]
+    else:
+        zh, zc = split_f32c(z0)
+        dh, dc = split_f32c(dp0)
+        t = [dev(a, torch.float32) for a in (zh, dh, zc, dc)]
+        ltrk.ltrk_track_f32c(t[0], t[1], t[2], t[3], turns, SPS_RING, integ, mom)
+        out = [t[0], t[1], t[2], t[3]]
+    torch.cuda.synchronize()
+    ltrk.ltrk_set_plan()
+    return [x.cpu().numpy() for x in out] + [mom.cpu().numpy()]
+
+
+def test_engine_mix_equals_alone(ltrk):
+    eng = ltrk.Engine(hbm_budget_bytes=64 << 20, max_slots=8)
+    inits = [gaussian_bunch(n, 0.2, 1e-3, 500 + i) for i, (n, *_r) in enumerate(JOBS)]
+    slots = {}
+    # admit the first three, step, then admit the rest while those are running
+    for i in range(3):
+        n, T, integ, dt = JOBS[i]
+        z0, dp0 = inits[i]
+        if dt == "f64":
+            slots[i] = eng.admit(n, T, SPS_RING, integ, dt, z0, dp0)
+        else:
+            zh, zc = split_f32c(z0)
+            dh, dc = split_f32c(dp0)
+            slots[i] = eng.admit(n, T, SPS_RING, integ, dt, zh, dh, zc, dc)
+    eng.step(64)
+    for i in range(3, len(JOBS)):
+        n, T, integ, dt = JOBS[i]
+        z0, dp0 = inits[i]
+        zh, zc = split_f32c(z0)
+        dh, dc = split_f32c(dp0)
+        if dt == "f64":
+            slots[i] = eng.admit(n, T, SPS_RING, integ, dt, z0, dp0)
+        else:
+            slots[i] = eng.admit(n, T, SPS_RING, integ, dt, zh, dh, zc, dc)
+    results = {}
+    for _ in range(100):
+        if len(results) == len(JOBS):
+            break
+        eng.step(50)
+        for i, s in slots.items():
+            if i not in results and eng.poll(s):
+                results[i] = eng.result(s)
+                eng.retire(s)
+    assert len(results) == len(JOBS)
+    for i, (n, T, integ, dt) in enumerate(JOBS):
+        z0, dp0 = inits[i]
+        ref = alone(ltrk, n, T, integ, dt, z0, dp0)
+        got = results[i]
+        if dt == "f64":
+            pairs = [(got[0], ref[0]), (got[1], ref[1]), (got[2], ref[2])]
+        else:
+            # engine returns (z, dp, z_comp, dp_comp, mom); alone (z, dp, zc, dc, mom)
+            pairs = list(zip(got, ref))
+        for a, b in pairs:
+            assert np.array_equal(a, b), (i, JOBS[i])
+    st = eng.stats()
+    assert st["active_slots"] == 0 and st["arena_free_bytes"] == st["arena_bytes"]
+    eng.close()
+
+
+def test_engine_admission_limits(ltrk):
+    fp = ltrk.ltrk_engine_footprint(10_000, 100)
+    eng = ltrk.Engine(hbm_budget_bytes=2 * fp, max_slots=3)
+    z0, dp0 = gaussian_bunch(10_000, 0.2, 1e-3, 1)
+    a = eng.admit(10_000, 100, SPS_RING, "leapfrog", "f64", z0, dp0)
+    b = eng.admit(10_000, 100, SPS_RING, "leapfrog", "f64", z0, dp0)
+    with pytest.raises(ltrk.EngineBusy):          # budget exhausted
+        eng.admit(10_000, 100, SPS_RING, "leapfrog", "f64", z0, dp0)
+    with pytest.raises(ltrk.LtrkError):           # can never fit
+        eng.admit(100_000, 100, SPS_RING, "leapfrog", "f64", np.zeros(100_000), np.zeros(100_000))
+    eng.cancel(b)
+    eng.step(30)
+    assert eng.poll(b)                             # cancelled: no further turns
+    eng.retire(b)
+    c = eng.admit(10_000, 100, SPS_RING, "leapfrog", "f64", z0, dp0)
+    with pytest.raises(ltrk.EngineBusy):          # all arena blocks taken again
+        eng.admit(10, 10, SPS_RING, "leapfrog", "f64", z0[:10], dp0[:10])
+    for _ in range(10):
+        eng.step(50)
+    assert eng.poll(a) and eng.poll(c)
+    z, dp, mom = eng.result(a)
+    z2, dp2, mom2 = eng.result(c)
+    assert np.array_equal(z, z2) and np.array_equal(mom, mom2)
+    eng.close()

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (FP64): after 1e3 turns, e <= 1e-12 for particles away from the
+separatrix and e <= 1e-10 near it (norm in tests/_parity.py); moments to
+1e-10 relative. The GPU evaluates sin(k z) with its own revolution-reduced
+polynomial and fused multiply-adds, the oracle with libm sin and separate
+roundings, so the two differ by a few ulp per turn; the bounds leave two
+orders of magnitude over the growth of such differences on these orbits.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import SPS_RING, SIGMA_DP, SIGMA_Z, SEEDS, gaussian_bunch
+from tests._parity import bucket_error, moment_error, near_separatrix
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+INTEGS = ["euler_cromer", "leapfrog", "ruth4", "rk4"]
+
+
+@pytest.fixture(scope="module")
+def ltrk():
+    import paper_1610_05801_amd as m
+    yield m
+    m.ltrk_set_plan()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def run_f64(ltrk, z0, dp0, turns, integ, ring=SPS_RING, moments=True, stream=None):
+    z, dp = dev(z0), dev(dp0)
+    mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda") if moments else None
+    ltrk.ltrk_track_f64(z, dp, turns, ring, integ, mom, stream=stream)
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), dp.cpu().numpy(), (mom.cpu().numpy() if moments else None)
+
+
+def check_against_oracle(z, dp, mom, z0, dp0, turns, integ, ring=SPS_RING,
+                         core_tol=1e-12, sep_tol=1e-10, mom_tol=1e-10):
+    zr, dr, mr = oracle.track(z0, dp0, turns, ring, integ)
+    e = bucket_error(z, dp, zr, dr, ring)
+    near = near_separatrix(z0, dp0, ring)
+    assert np.all(np.isfinite(e))
+    if np.any(~near):
+        assert e[~near].max() <= core_tol, (integ, e[~near].max())
+    if np.any(near):
+        assert e[near].max() <= sep_tol, (integ, e[near].max())
+    if mom is not None and z0.size > 1:
+        assert moment_error(mom, mr).max() <= mom_tol
+    return e, near
+
+
+@pytest.mark.parametrize("integ", INTEGS)
+def test_small_workload_all_schemes(ltrk, integ):
+    """1e3 particles, 1e3 turns, the small seeded Gaussian bunch."""
+    z0, dp0 = gaussian_bunch(1000, SIGMA_Z, SIGMA_DP, SEEDS["small"])
+    z, dp, mom = run_f64(ltrk, z0, dp0, 1000, integ)
+    check_against_oracle(z, dp, mom, z0, dp0, 1000, integ)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 257, 4097, 100_003])
+@pytest.mark.parametrize("ppl", [1, 2, 4, 8])
+def test_sizes_and_tiles(ltrk, n, ppl):
+    """Ragged tails and several tiles for every particles-per-lane value."""
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, 7000 + n)
+    ltrk.ltrk_set_plan(7, 128, ppl, 0)
+    try:
+        z, dp, mom = run_f64(ltrk, z0, dp0, 100, "leapfrog")
+    finally:
+        ltrk.ltrk_set_plan()
+    check_against_oracle(z, dp, mom, z0, dp0, 100, "leapfrog")
+    if n == 1:
+        assert np.all(mom[:, 1] == 0.0) and np.all(mom[:, 4] == 0.0)
+        assert np.array_equal(mom[-1, [0, 2]], [z[0], dp[0]])
+
+
+def test_invariance_across_k_block_graph_and_split(ltrk):
+    """Same particles-per-lane: bitwise-identical state and moments for any
+    turns-per-launch (1 = one launch per turn), block size, graph replay, and
+    for T turns run as T1 + T2."""
+    z0, dp0 = gaussian_bunch(50_000, SIGMA_Z, SIGMA_DP, 11)
+    T = 97
+    ref = None
+    stream = torch.cuda.Stream()
+    for K, block, graph in [(1, 256, 0), (5, 64, 0), (64, 128, 1), (128, 256, 1), (97, 256, 1)]:
+        ltrk.ltrk_set_plan(K, block, 4, graph)
+        with torch.cuda.stream(stream):
+            out = run_f64(ltrk, z0, dp0, T, "ruth4", stream=stream)
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b), (K, block, graph)
+    # graph replay a second time (cached graph)
+    ltrk.ltrk_set_plan(64, 128, 4, 1)
+    with torch.cuda.stream(stream):
+        again = run_f64(ltrk, z0, dp0, T, "ruth4", stream=stream)
+    for a, b in zip(again, ref):
+        assert np.array_equal(a, b)
+    # checkpoint / resume: 40 + 57 turns
+    z, dp = dev(z0), dev(dp0)
+    m1 = torch.empty((40, 5), dtype=torch.float64, device="cuda")
+    m2 = torch.empty((57, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_track_f64(z, dp, 40, SPS_RING, "ruth4", m1)
+    ltrk.ltrk_track_f64(z, dp, 57, SPS_RING, "ruth4", m2)
+    torch.cuda.synchronize()
+    ltrk.ltrk_set_plan()
+    assert np.array_equal(z.cpu().numpy(), ref[0])
+    assert np.array_equal(dp.cpu().numpy(), ref[1])
+    assert np.array_equal(np.vstack([m1.cpu().numpy(), m2.cpu().numpy()]), ref[2])
+
+
+def test_moments_only_entry_point(ltrk):
+    z0, dp0 = gaussian_bunch(123_457, SIGMA_Z, SIGMA_DP, 5)
+    dp0 = dp0 + 0.2e-3 * z0 / SIGMA_Z
+    out = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_moments_f64(dev(z0), dev(dp0), out)
+    got = out.cpu().numpy()[0]
+    ref = oracle.moments(z0, dp0)
+    assert abs(got[0] - ref[0]) <= 1e-13 * ref[1]
+    assert abs(got[2] - ref[2]) <= 1e-13 * ref[3]
+    for j in (1, 3, 4):
+        assert abs(got[j] - ref[j]) <= 1e-12 * ref[j]
+
+
+def test_empty_and_zero_turn_calls(ltrk):
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    mom = torch.zeros((3, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_track_f64(z, z, 3, SPS_RING, "leapfrog", mom)
+    torch.cuda.synchronize()
+    assert torch.isnan(mom).all()
+    z0, dp0 = gaussian_bunch(10, SIGMA_Z, SIGMA_DP, 1)
+    zt, dt = dev(z0), dev(dp0)
+    ltrk.ltrk_track_f64(zt, dt, 0, SPS_RING, "leapfrog", None)
+    torch.cuda.synchronize()
+    assert np.array_equal(zt.cpu().numpy(), z0)
+
+
+def test_rejects_short_buffers(ltrk):
+    z = torch.zeros(100, dtype=torch.float64, device="cuda")
+    mom = torch.zeros((4, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(ltrk.LtrkError):
+        ltrk.ltrk_track_f64(z, z, 5, SPS_RING, "leapfrog", mom)   # 5 rows needed
+    torch.cuda.synchronize()
+
+
+def test_paper_scale_sampled(ltrk):
+    """1e6 particles, 1e4 turns (the benchmark workload and launch plan): a
+    strided sample of 1000 particles against the oracle run on exactly those
+    particles (particles are independent), and the last moment row against the
+    oracle's two-pass moments of the GPU's final state."""
+    n, T = 1_000_000, 10_000
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        z, dp, mom = run_f64(ltrk, z0, dp0, T, "leapfrog", stream=stream)
+    idx = np.arange(0, n, n // 1000)
+    zr, dr, _ = oracle.track(z0[idx], dp0[idx], T, SPS_RING, "leapfrog", with_moments=False)
+    e = bucket_error(z[idx], dp[idx], zr, dr, SPS_RING)
+    near = near_separatrix(z0[idx], dp0[idx], SPS_RING)
+    assert e[~near].max() <= 1e-10
+    if near.any():
+        assert e[near].max() <= 1e-6
+    last = oracle.moments(z, dp)
+    err = moment_error(mom[-1:], last[None, :])
+    assert err.max() <= 1e-12
