@@ -1,0 +1,604 @@
+"""Benchmark of the longitudinal tracking hot path on one MI355X.
+
+Default (the driver's contract): one step = tracking 1e6 particles for 1e4
+turns with FP64 leap-frog and moments after every turn (host constants, the
+fused turn kernels and the moment finalize: the whole hot path) on its own
+copy of a seeded Gaussian bunch already resident in HBM. Prints ONE JSON line
+on stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+
+Other workloads (--workload): unfused (one launch per turn, HBM roofline
+sweep), precision (FP32+Kahan vs FP64, 1e7 particles), batched (256 uneven
+bunches), serving (Poisson request stream through the engine), ksweep.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("particle-turns/sec, FP64 leap-frog, 10^6 particles; FP32 vs FP64; "
+          "p50/p99 latency")
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+# Algorithmic FP64 flops per particle-turn (FMA = 2), see the design doc:
+# sin(k z) = phase multiply + reduction subtract + r^2 + 8 FMA + final multiply = 20.
+SIN_FLOPS = 20
+FLOPS_PER_PT = {
+    "euler_cromer": 2 + 2 + SIN_FLOPS + 8,
+    "leapfrog": 4 + 2 + SIN_FLOPS + 8,
+    "ruth4": 8 + 6 + 3 * SIN_FLOPS + 8,
+    "rk4": 32 + 4 * SIN_FLOPS + 8,
+}
+STATE_BYTES_PER_PARTICLE = 16  # z, dp FP64 (or FP32 hi + comp for both)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1610_05801_amd", "csrc")
+    for f in ("kernels.hip", "ltrk_device.h", "sinpi_coeffs.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str, launch_units: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when missing or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    per_unit = d.get("hbm_bytes_per_particle_turn")
+    return None if per_unit is None else per_unit * launch_units
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
+    """The FP64 oracle on the host cores: a bounded sample of the workload
+    (the same bunch, its first T turns), scaled to particle-turns/s."""
+    import oracle
+    from synth import SIGMA_DP, SIGMA_Z, gaussian_bunch
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    z, dp, _ = oracle.track(z0, dp0, 2, ring, "leapfrog", threads=threads)
+    per_turn = (time.perf_counter() - t0) / 2
+    turns = int(max(2, min(turns_total, budget_s / max(per_turn, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.track(z0, dp0, turns, ring, "leapfrog", threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * turns / dt, "unit": "particle-turns/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d particles x first %d of %d turns, leap-frog FP64 with moments every "
+                      "turn, OpenMP over particles, %.1f s wall" % (n, turns, turns_total, dt)}
+
+
+def bench_default(args):
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch, split_f32c
+
+    n, T = args.particles, args.turns
+    integ = "leapfrog"
+    seed = SEEDS["paper_scale"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    log("bench: %d particles x %d turns, %s FP64" % (n, T, integ))
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
+    zt, dt = torch.as_tensor(z0), torch.as_tensor(dp0)
+    if args.tune:
+        plan = ltrk.ltrk_autotune(integ, "f64", n, stream=stream)
+        log("autotuned plan", plan)
+    plan = ltrk.ltrk_get_plan(integ, "f64", n)
+    nsteps = args.warmup + args.steps
+    # every step tracks its own copy of the initial bunch (inputs resident in HBM)
+    zs = [zt.to(dev) for _ in range(nsteps)]
+    ds = [dt.to(dev) for _ in range(nsteps)]
+    moms = [torch.empty((T, 5), dtype=torch.float64, device=dev) for _ in range(2)]
+    torch.cuda.synchronize()
+
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            ltrk.ltrk_track_f64(zs[i], ds[i], T, SPS_RING, integ, moms[i % 2], stream=stream)
+        stream.synchronize()
+        ltrk.ltrk_timing_enable(True)
+        ltrk.ltrk_timing_take()
+        step_ms = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(args.warmup, nsteps):
+            t0 = time.perf_counter()
+            ltrk.ltrk_track_f64(zs[i], ds[i], T, SPS_RING, integ, moms[i % 2], stream=stream)
+            stream.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        tm = ltrk.ltrk_timing_take()
+        ltrk.ltrk_timing_enable(False)
+    value = n * T * args.steps / elapsed
+    log("fused: %.4e particle-turns/s, %.3f ms/step" % (value, elapsed / args.steps * 1e3))
+    avg_track_ms = tm["track_ms"] / max(tm["track_launches"], 1)
+    launch_turns = T * args.steps / max(tm["track_launches"], 1)
+    launch_pt = n * launch_turns
+    flops = FLOPS_PER_PT[integ] * launch_pt
+    achieved = flops / (avg_track_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": load_traffic("fused_leapfrog_f64_1e6_traffic.json", launch_pt),
+                "kernel": "k_track_single<leapfrog,f64,P=%d>" % plan["ppl"],
+                "avg_launch_ms": avg_track_ms, "turns_per_launch": launch_turns,
+                "flops_per_particle_turn": FLOPS_PER_PT[integ],
+                "finalize_ms_per_step": tm["finalize_ms"] / args.steps}
+
+    extras = {}
+    if not args.quick:
+        # FP32 + Kahan state on the same workload (2 steps)
+        zh, zc = split_f32c(z0)
+        dh, dc = split_f32c(dp0)
+        f32 = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+        with torch.cuda.stream(stream):
+            ltrk.ltrk_track_f32c(*[a.clone() for a in f32], T, SPS_RING, integ, moms[0],
+                                 stream=stream)
+            stream.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ltrk.ltrk_track_f32c(*[a.clone() for a in f32], T, SPS_RING, integ, moms[0],
+                                     stream=stream)
+            stream.synchronize()
+            f32_s = (time.perf_counter() - t0) / reps
+        v32 = n * T / f32_s
+        extras["f32c"] = {"value": v32, "unit": "particle-turns/s", "ms_per_step": f32_s * 1e3,
+                          "ratio_to_f64": v32 / value}
+        log("f32c: %.4e particle-turns/s" % v32)
+        # one launch per turn (HBM-bound form) on the same workload, 1e3 turns
+        Tu = min(T, 1000)
+        saved = ltrk.ltrk_get_plan(integ, "f64", n)
+        ltrk.ltrk_set_plan(1, plan["block"], plan["ppl"], 1)
+        z1, d1 = zt.to(dev), dt.to(dev)
+        mu = torch.empty((Tu, 5), dtype=torch.float64, device=dev)
+        with torch.cuda.stream(stream):
+            ltrk.ltrk_track_f64(z1, d1, Tu, SPS_RING, integ, mu, stream=stream)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            ltrk.ltrk_track_f64(z1, d1, Tu, SPS_RING, integ, mu, stream=stream)
+            stream.synchronize()
+            du = time.perf_counter() - t0
+        ltrk.ltrk_set_plan()
+        extras["unfused"] = {"value": n * Tu / du, "unit": "particle-turns/s",
+                             "hbm_GBps_algorithmic": STATE_BYTES_PER_PARTICLE * 2 * n * Tu / du / 1e9,
+                             "turns": Tu, "note": "16 MB state is cache resident at 1e6 "
+                             "particles; the HBM roofline sweep is --workload unfused"}
+        log("unfused: %.4e particle-turns/s" % (n * Tu / du))
+        del saved
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-turns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "leap-frog FP64, 1e6 particles x 1e4 turns, moments every turn",
+                   "particles": n, "turns": T, "integrator": integ, "seed": seed,
+                   "ring": "C=6911 m, h=4620, V=2 MV, p0c=26 GeV, m=0.938 GeV, gamma_t=22.77",
+                   "plan": plan},
+        "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99),
+                       "unit": "ms per step (1e10 particle-turns)"},
+        "roofline": roofline,
+    }
+    out.update(extras)
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(n, T, SPS_RING, seed, budget_s=args.cpu_seconds)
+        log("cpu: %.4e particle-turns/s on %d threads" % (out["cpu_baseline"]["value"],
+                                                           out["cpu_baseline"]["cores"]))
+    print(json.dumps(out), flush=True)
+
+
+def _timed_track(ltrk, torch, stream, n, turns, integ, dtype, arrays, mom, reps=1):
+    """Run reps calls (after one warm-up); returns (wall seconds per call, timing dict)."""
+    from synth import SPS_RING
+    fn = ltrk.ltrk_track_f64 if dtype == "f64" else ltrk.ltrk_track_f32c
+    with torch.cuda.stream(stream):
+        fn(*arrays, turns, SPS_RING, integ, mom, stream=stream)
+        stream.synchronize()
+        ltrk.ltrk_timing_enable(True)
+        ltrk.ltrk_timing_take()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn(*arrays, turns, SPS_RING, integ, mom, stream=stream)
+        stream.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        tm = ltrk.ltrk_timing_take()
+        ltrk.ltrk_timing_enable(False)
+    return dt, tm
+
+
+def bench_unfused(args):
+    """One launch per turn (K = 1): the HBM-bound form, swept in n up to far
+    beyond the 256 MB last-level cache."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    for n in (1_000_000, 10_000_000, 100_000_000, 250_000_000):
+        turns = 200 if n <= 10_000_000 else 30
+        ltrk.ltrk_set_plan(1, 256, 4, 1)
+        g = torch.Generator(device=dev).manual_seed(7)
+        z = torch.randn(n, dtype=torch.float64, device=dev, generator=g) * 0.23
+        dp = torch.randn(n, dtype=torch.float64, device=dev, generator=g) * 1e-3
+        mom = torch.empty((turns, 5), dtype=torch.float64, device=dev)
+        dt, tm = _timed_track(ltrk, torch, stream, n, turns, "leapfrog", "f64", (z, dp), mom)
+        kern_ms = tm["track_ms"] / max(tm["track_launches"], 1)
+        alg_bytes = STATE_BYTES_PER_PARTICLE * 2 * n
+        row = {"particles": n, "turns": turns, "particle_turns_per_s": n * turns / dt,
+               "avg_kernel_ms": kern_ms, "achieved_GBps": alg_bytes / (kern_ms * 1e-3) / 1e9,
+               "frac_hbm": alg_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "finalize_ms_per_turn": tm["finalize_ms"] / turns}
+        rows.append(row)
+        log(json.dumps(row))
+        del z, dp, mom
+        torch.cuda.empty_cache()
+    ltrk.ltrk_set_plan()
+    print(json.dumps({"workload": "unfused leap-frog FP64, one launch per turn", "rows": rows,
+                      "bytes_per_particle_turn": 32, "peak_GBps": HBM_PEAK_GBS}), flush=True)
+
+
+def bench_ksweep(args):
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n, T = args.particles, min(args.turns, 4096)
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    rows = []
+    base = ltrk.ltrk_get_plan("leapfrog", "f64", n)
+    for ppl in (2, 4, 8):
+        for K in (1, 8, 16, 32, 64, 128, 256, 512):
+            for graph in (0, 1):
+                ltrk.ltrk_set_plan(K, base["block"], ppl, graph)
+                z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+                mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+                from synth import SPS_RING
+                with torch.cuda.stream(stream):
+                    ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom, stream=stream)
+                    stream.synchronize()
+                    t0 = time.perf_counter()
+                    ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom, stream=stream)
+                    stream.synchronize()
+                    dt = time.perf_counter() - t0
+                row = {"K": K, "ppl": ppl, "graph": graph, "block": base["block"],
+                       "particle_turns_per_s": n * T / dt}
+                rows.append(row)
+                log(json.dumps(row))
+    ltrk.ltrk_set_plan()
+    print(json.dumps({"workload": "K sweep, leap-frog FP64, %d particles x %d turns" % (n, T),
+                      "rows": rows}), flush=True)
+
+
+def bench_precision(args):
+    """FP32 + Kahan vs FP64 at 1e7 particles x 1e5 turns (LF, EC, Ruth4), with
+    the oracle on a strided 1e4-particle subset."""
+    import torch
+    import oracle
+    import paper_1610_05801_amd as ltrk
+    from synth import (SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch, join_f32c,
+                       split_f32c)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n = args.particles if args.particles != 1_000_000 else 10_000_000
+    T = args.turns if args.turns != 10_000 else 100_000
+    z_in, dp_in = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["precision"])
+    zh, zc = split_f32c(z_in)
+    dh, dc = split_f32c(dp_in)
+    z0, dp0 = join_f32c(zh, zc), join_f32c(dh, dc)     # identical start for both paths
+    idx = np.arange(0, n, max(1, n // 10_000))
+    c = oracle.derive(SPS_RING)
+    zb, db = c["bucket_half_length"], c["bucket_height"]
+    h0 = oracle.hamiltonian(z0[idx], dp0[idx], SPS_RING)
+    core = np.abs(h0 - c["H_sep"]) / abs(c["H_sep"]) > 0.01
+    inside = h0 > c["H_sep"]
+    results = []
+    for integ in ("leapfrog", "euler_cromer", "ruth4"):
+        t0 = time.perf_counter()
+        zr, dr, mr = oracle.track(z0[idx], dp0[idx], T, SPS_RING, integ,
+                                  threads=len(os.sched_getaffinity(0)))
+        oracle_s = time.perf_counter() - t0
+        out = {"integrator": integ}
+        finals = {}
+        for dtype in ("f64", "f32c"):
+            if dtype == "f64":
+                arrays = (torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev))
+            else:
+                arrays = tuple(torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc))
+            mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+            fn = ltrk.ltrk_track_f64 if dtype == "f64" else ltrk.ltrk_track_f32c
+            with torch.cuda.stream(stream):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn(*arrays, T, SPS_RING, integ, mom, stream=stream)
+                stream.synchronize()
+                dt = time.perf_counter() - t0
+            a = [x.cpu().numpy() for x in arrays]
+            zf, df = (a[0], a[1]) if dtype == "f64" else (join_f32c(a[0], a[2]), join_f32c(a[1], a[3]))
+            finals[dtype] = (zf, df, mom.cpu().numpy())
+            e = np.hypot((zf[idx] - zr) / zb, (df[idx] - dr) / db) / np.hypot(zr / zb, dr / db)
+            hn = oracle.hamiltonian(zf[idx], df[idx], SPS_RING)
+            hr = oracle.hamiltonian(zr, dr, SPS_RING)
+            dh_gpu = np.abs(hn - h0)[inside & core] / abs(c["H_sep"])
+            dh_ref = np.abs(hr - h0)[inside & core] / abs(c["H_sep"])
+            out[dtype] = {"particle_turns_per_s": n * T / dt, "seconds": dt,
+                          "subset_e_core_max": float(e[core].max()),
+                          "subset_e_core_p50": float(np.median(e[core])),
+                          "subset_e_core_p99": float(np.percentile(e[core], 99)),
+                          "dH_over_Hsep_max_inside": float(dh_gpu.max()),
+                          "dH_over_Hsep_max_inside_oracle": float(dh_ref.max())}
+        # full-population moments: F32C against FP64 (both GPU, same start)
+        m64, m32 = finals["f64"][2], finals["f32c"][2]
+        rel = np.abs(m32 - m64) / np.abs(m64)
+        rel[:, 0] = np.abs(m32[:, 0] - m64[:, 0]) / m64[:, 1]
+        rel[:, 2] = np.abs(m32[:, 2] - m64[:, 2]) / m64[:, 3]
+        out["f32c_vs_f64_moments_max_rel"] = dict(zip(
+            ["mean_z", "rms_z", "mean_dp", "rms_dp", "emit"], rel.max(axis=0).tolist()))
+        out["f32c_vs_f64_moments_final_rel"] = dict(zip(
+            ["mean_z", "rms_z", "mean_dp", "rms_dp", "emit"], rel[-1].tolist()))
+        out["oracle_subset_seconds"] = oracle_s
+        results.append(out)
+        log(json.dumps(out))
+    print(json.dumps({"workload": "precision: %d particles x %d turns, F32C vs FP64" % (n, T),
+                      "subset": int(idx.size), "results": results}), flush=True)
+
+
+def _matched_sigma_z(ltrk, ring, sigma_dp):
+    d = ltrk.ltrk_derive(ring)
+    return sigma_dp * d["slip_length"] / d["omega_s"]
+
+
+def bench_batched(args):
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import batched_specs, gaussian_bunch, ring_for, split_f32c
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    T = args.turns
+    specs = batched_specs()
+    total = sum(s.n for s in specs)
+    log("batched: %d bunches, %d particles, %d turns" % (len(specs), total, T))
+    res = {"workload": "batched: %d bunches (log-uniform 1e3-1e6), %d turns" % (len(specs), T),
+           "particles": total}
+    for dtype in ("f64", "f32c"):
+        plan = ltrk.ltrk_autotune("leapfrog", dtype, total // len(specs) * 4, stream=stream) \
+            if args.tune else ltrk.ltrk_get_plan("leapfrog", dtype, total)
+        bunches = []
+        for s in specs:
+            r = ring_for(s)
+            z0, dp0 = gaussian_bunch(s.n, _matched_sigma_z(ltrk, r, s.sigma_dp), s.sigma_dp, s.seed)
+            b = {"ring": r, "moments": torch.empty((T, 5), dtype=torch.float64, device=dev)}
+            if dtype == "f64":
+                b["z"], b["dp"] = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+            else:
+                zh, zc = split_f32c(z0)
+                dh, dc = split_f32c(dp0)
+                b["z"], b["dp"], b["z_comp"], b["dp_comp"] = [torch.as_tensor(a).to(dev)
+                                                              for a in (zh, dh, zc, dc)]
+            bunches.append(b)
+        with torch.cuda.stream(stream):
+            ltrk.ltrk_track_batched(bunches, 64, "leapfrog", dtype, stream=stream)   # warm-up
+            stream.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ltrk.ltrk_track_batched(bunches, T, "leapfrog", dtype, stream=stream)
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+        res[dtype] = {"particle_turns_per_s": total * T / dt, "seconds": dt, "plan": plan}
+        log(dtype, json.dumps(res[dtype]))
+        del bunches
+        torch.cuda.empty_cache()
+    print(json.dumps(res), flush=True)
+
+
+def bench_serving(args):
+    """Poisson request stream through the continuous-batching engine."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from paper_1610_05801_amd.serve import Request, run_stream
+    from synth import gaussian_bunch, request_stream, split_f32c, SPS_RING
+    count = args.requests
+    budget = int(args.budget_gb * (1 << 30))
+    probe = request_stream(1.0, count)
+    work = np.array([r.n * r.turns for r in probe], dtype=np.float64)
+    # capacity estimate: mean work per request over a measured mixed rate
+    rate_pt = args.capacity_rate
+    capacity = rate_pt / work.mean()
+    log("serving: %d requests, mean work %.3e particle-turns, capacity ~%.2f req/s"
+        % (count, work.mean(), capacity))
+    out = {"workload": "serving: Poisson requests, n log-uniform 1e3-1e7, turns 1e3-1e5, "
+                       "EC/LF/Ruth4 x F64/F32C", "requests": count, "budget_bytes": budget,
+           "capacity_req_per_s_estimate": capacity, "rows": []}
+    for frac in args.load:
+        lam = frac * capacity
+        specs = request_stream(lam, count)
+        reqs = []
+        for sp in specs:
+            r = dict(SPS_RING, voltage_V=sp.voltage_V, harmonic=sp.harmonic)
+            z0, dp0 = gaussian_bunch(sp.n, _matched_sigma_z(ltrk, r, sp.sigma_dp), sp.sigma_dp,
+                                     sp.seed)
+            state = (z0, dp0)
+            if sp.dtype == "f32c":
+                zh, zc = split_f32c(z0)
+                dh, dc = split_f32c(dp0)
+                state = (zh, dh, zc, dc)
+            reqs.append(Request(sp.rid, sp.arrival_s, sp.n, sp.turns, r, sp.integrator,
+                                sp.dtype, state))
+        eng = ltrk.Engine(budget, max_slots=args.slots)
+        recs, wall = run_stream(eng, reqs, k=args.k)
+        eng.close()
+        lat = np.array([x.latency_s for x in recs])
+        pt = sum(x.n * x.turns for x in recs)
+        row = {"load": frac, "rate_req_per_s": lam, "p50_latency_s": float(np.percentile(lat, 50)),
+               "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+               "wall_s": wall, "particle_turns_per_s": pt / wall, "completed": len(recs)}
+        out["rows"].append(row)
+        log(json.dumps(row))
+        del reqs
+    print(json.dumps(out), flush=True)
+
+
+COUNTER_CAL_BYTES = 1 << 29   # 512 MiB read + 512 MiB written by the calibration kernel
+
+
+def bench_counters(args):
+    """Kernels for rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, SQ_*): a
+    calibration multiply-by-one of known size, the fused leap-frog kernel at
+    1e6 particles (K = 128, 4 launches) and the one-launch-per-turn kernel at
+    1e8 particles (5 turns)."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    src = torch.ones(COUNTER_CAL_BYTES // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    n = 1_000_000
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+    plan = ltrk.ltrk_get_plan("leapfrog", "f64", n)
+    ltrk.ltrk_set_plan(128, plan["block"], plan["ppl"], 0)
+    mom = torch.empty((512, 5), dtype=torch.float64, device=dev)
+    ltrk.ltrk_track_f64(z, dp, 512, SPS_RING, "leapfrog", mom)
+    torch.cuda.synchronize()
+    n2 = 100_000_000
+    g = torch.Generator(device=dev).manual_seed(7)
+    z2 = torch.randn(n2, dtype=torch.float64, device=dev, generator=g) * 0.23
+    d2 = torch.randn(n2, dtype=torch.float64, device=dev, generator=g) * 1e-3
+    ltrk.ltrk_set_plan(1, 256, 4, 0)
+    mom2 = torch.empty((5, 5), dtype=torch.float64, device=dev)
+    ltrk.ltrk_track_f64(z2, d2, 5, SPS_RING, "leapfrog", mom2)
+    torch.cuda.synchronize()
+    ltrk.ltrk_set_plan()
+    print(json.dumps({"workload": "counters", "fused_plan": dict(plan, turns_per_launch=128),
+                      "calibration_bytes": COUNTER_CAL_BYTES}), flush=True)
+
+
+def summarize_counters(fetch_csv, write_csv, out_path, ppl):
+    """Condense two rocprofv3 --pmc CSVs (FETCH_SIZE run, WRITE_SIZE run) into
+    HBM bytes per particle-turn for the fused and unfused kernels, scaled by
+    what the same counters read for the calibration kernel."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(
+                    (int(r.get("Dispatch_Id", 0)), float(r["Counter_Value"])))
+        return rows
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, key):
+        return [v for k, vs in d.items() if key(k) for _, v in sorted(vs)]
+
+    cal_f = pick(fetch, lambda k: "mul" in k.lower() or "elementwise" in k.lower())
+    cal_w = pick(write, lambda k: "mul" in k.lower() or "elementwise" in k.lower())
+    fus_f = pick(fetch, lambda k: "k_track_single" in k)
+    fus_w = pick(write, lambda k: "k_track_single" in k)
+    kib = COUNTER_CAL_BYTES / 1024.0
+    f_scale = kib / np.median(cal_f)
+    w_scale = kib / np.median(cal_w)
+    # k_track_single dispatches: 4 fused (1e6 x 128 turns) then 5 unfused (1e8 x 1 turn)
+    fused = {"fetch_bytes": float(np.median(fus_f[:4])) * 1024 * f_scale,
+             "write_bytes": float(np.median(fus_w[:4])) * 1024 * w_scale, "particle_turns": 1e6 * 128}
+    unfused = {"fetch_bytes": float(np.median(fus_f[4:])) * 1024 * f_scale,
+               "write_bytes": float(np.median(fus_w[4:])) * 1024 * w_scale, "particle_turns": 1e8}
+    out = {"kernel_hash": kernel_source_hash(), "ppl": ppl,
+           "calibration": {"bytes_each_way": COUNTER_CAL_BYTES, "fetch_scale": f_scale,
+                           "write_scale": w_scale},
+           "fused_leapfrog_1e6_K128": fused, "unfused_leapfrog_1e8": unfused,
+           "hbm_bytes_per_particle_turn": (fused["fetch_bytes"] + fused["write_bytes"]) / fused["particle_turns"],
+           "unfused_hbm_bytes_per_particle_turn":
+               (unfused["fetch_bytes"] + unfused["write_bytes"]) / unfused["particle_turns"]}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
+                             "counters"])
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--turns", type=int, default=10_000)
+    ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
+    ap.add_argument("--quick", action="store_true", help="skip the FP32 and unfused legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--requests", type=int, default=500)
+    ap.add_argument("--budget-gb", type=float, default=2.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--k", type=int, default=256)
+    ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8, 1.0])
+    ap.add_argument("--capacity-rate", type=float, default=6.0e11,
+                    help="particle-turns/s assumed for the capacity estimate")
+    ap.add_argument("--summarize", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "PPL"),
+                    help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(particles would shard by range with one final moment-sum reduction; "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.summarize:
+        summarize_counters(args.summarize[0], args.summarize[1], args.summarize[2],
+                           int(args.summarize[3]))
+        return
+    {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
+     "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
+     "counters": bench_counters}[args.workload](args)
+
+
+if __name__ == "__main__":
+    main()

@@ -18,7 +18,26 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libltrk.so is not built: run `python -m paper_1610_05801_amd.build` "
                       "(or __graft_entry__.build())")
 
+# PyTorch ships its own HIP runtime (same SONAME as the system one). Loading
+# torch first makes libltrk bind to that already-loaded runtime, so device
+# pointers and streams from torch are valid inside the library; loading
+# libltrk first would pull in a second HIP runtime that sees no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({line.split()[-1] for line in f if "libamdhip64" in line})
+    except OSError:
+        return []
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded in this process (%s); import torch before "
+                      "anything that loads libamdhip64" % ", ".join(_hip_runtimes()))
 
 LTRK_OK = 0
 LTRK_EINVAL = -1

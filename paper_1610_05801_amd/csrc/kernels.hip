@@ -23,7 +23,9 @@
 //
 // The RF kick evaluates sin(k z) as sin(pi u), u = (2h/C) z in half
 // revolutions: n = rint(u), r = u - n is exact (Sterbenz) and |r| <= 1/2, the
-// polynomial of gen_sinpi.py gives sin(pi r), and (-1)^n restores the sign.
+// polynomial of gen_sinpi.py (with the kick weight folded into its
+// coefficients on the host) gives the scaled sin(pi r), and (-1)^n restores
+// the sign.
 // The reduction is branch-free and exact for any z, so particles that left
 // the bucket (large z) cost the same as the core.
 //
@@ -35,26 +37,43 @@
 
 #include "kernels.h"
 #include "ltrk_device.h"
-#include "sinpi_coeffs.h"
 
 namespace ltrk {
 
 // ---------------------------------------------------------------------------
 // Elementary operations
 
-__device__ __forceinline__ double sin_pi_u(double u) {
+// Kick terms for phase u (in half revolutions): returns r' and p with
+// r' * p = (scale) * sin(pi u), where q holds scale * kSinPiCoeff. n = rint(u),
+// r = u - n is exact (|r| <= 1/2), p = sum_j q[j] r^2j, and the sign (-1)^n is
+// applied to r: for |n| < 2^52 the parity of n is the last mantissa bit of
+// |n| + 2^52; larger |u| has r = 0, where the sign is moot.
+struct KickTerms {
+  double r, p;
+};
+
+__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
   const double n = __builtin_rint(u);
-  const double r = u - n;  // exact: |r| <= 1/2
+  const double r = u - n;
   const double s = r * r;
-  double p = kSinPiCoeff[kSinPiTerms - 1];
+  double p = q[kSinTerms - 1];
 #pragma unroll
-  for (int j = kSinPiTerms - 2; j >= 0; --j) p = __builtin_fma(p, s, kSinPiCoeff[j]);
-  const double y = r * p;
-  // (-1)^n: for |n| < 2^52 the parity of n is the last mantissa bit of
-  // |n| + 2^52; larger |u| has r = 0 and y = 0, where the sign is moot.
+  for (int j = kSinTerms - 2; j >= 0; --j) p = __builtin_fma(p, s, q[j]);
   const double t = __builtin_fabs(n) + 0x1p52;
   const uint64_t odd = (__builtin_bit_cast(uint64_t, t) & 1ull) << 63;
-  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, y) ^ odd);
+  return KickTerms{__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd), p};
+}
+
+// scale * sin(pi u) as one product.
+__device__ __forceinline__ double scaled_sin(double u, const double* __restrict__ q) {
+  const KickTerms k = kick_terms(u, q);
+  return k.r * k.p;
+}
+
+// delta + scale * sin(pi u) with the last product fused into the update.
+__device__ __forceinline__ double kicked(double d, double u, const double* __restrict__ q) {
+  const KickTerms k = kick_terms(u, q);
+  return __builtin_fma(k.r, k.p, d);
 }
 
 // Kahan-compensated x += inc with the running compensation c (value = x - c).
@@ -73,27 +92,27 @@ __device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) 
   const double s = c.half_rev_per_m;
   if constexpr (INTEG == kEulerCromer) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    d = kicked(d, z * s, c.kq[0]);
   } else if constexpr (INTEG == kLeapfrog) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    d = kicked(d, z * s, c.kq[0]);
     z = __builtin_fma(c.nd[0], d, z);
   } else if constexpr (INTEG == kRuth4) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    d = kicked(d, z * s, c.kq[0]);
     z = __builtin_fma(c.nd[1], d, z);
-    d = __builtin_fma(c.kw[1], sin_pi_u(z * s), d);
+    d = kicked(d, z * s, c.kq[1]);
     z = __builtin_fma(c.nd[1], d, z);
-    d = __builtin_fma(c.kw[0], sin_pi_u(z * s), d);
+    d = kicked(d, z * s, c.kq[0]);
     z = __builtin_fma(c.nd[0], d, z);
   } else if constexpr (INTEG == kRk4) {
-    const double k1z = c.neg_D * d, k1d = c.A * sin_pi_u(z * s);
+    const double k1z = c.neg_D * d, k1d = scaled_sin(z * s, c.kq[0]);
     const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
-    const double k2z = c.neg_D * d2, k2d = c.A * sin_pi_u(z2 * s);
+    const double k2z = c.neg_D * d2, k2d = scaled_sin(z2 * s, c.kq[0]);
     const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
-    const double k3z = c.neg_D * d3, k3d = c.A * sin_pi_u(z3 * s);
+    const double k3z = c.neg_D * d3, k3d = scaled_sin(z3 * s, c.kq[0]);
     const double z4 = z + k3z, d4 = d + k3d;
-    const double k4z = c.neg_D * d4, k4d = c.A * sin_pi_u(z4 * s);
+    const double k4z = c.neg_D * d4, k4d = scaled_sin(z4 * s, c.kq[0]);
     z = __builtin_fma(1.0 / 6.0, (k1z + 2.0 * k2z) + (2.0 * k3z + k4z), z);
     d = __builtin_fma(1.0 / 6.0, (k1d + 2.0 * k2d) + (2.0 * k3d + k4d), d);
   }
@@ -110,35 +129,35 @@ __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float
                                           const Coeffs& c) {
   const double s = c.half_rev_per_m;
   auto drift = [&](float ndf) { kahan_add(zh, zc, ndf * (dh - dc)); };
-  auto kick = [&](double kw) {
+  auto kick = [&](const double* q) {
     const double zv = static_cast<double>(zh) - static_cast<double>(zc);
-    kahan_add(dh, dc, static_cast<float>(kw * sin_pi_u(zv * s)));
+    kahan_add(dh, dc, static_cast<float>(scaled_sin(zv * s, q)));
   };
   if constexpr (INTEG == kEulerCromer) {
     drift(c.nd_f[0]);
-    kick(c.kw[0]);
+    kick(c.kq[0]);
   } else if constexpr (INTEG == kLeapfrog) {
     drift(c.nd_f[0]);
-    kick(c.kw[0]);
+    kick(c.kq[0]);
     drift(c.nd_f[0]);
   } else if constexpr (INTEG == kRuth4) {
     drift(c.nd_f[0]);
-    kick(c.kw[0]);
+    kick(c.kq[0]);
     drift(c.nd_f[1]);
-    kick(c.kw[1]);
+    kick(c.kq[1]);
     drift(c.nd_f[1]);
-    kick(c.kw[0]);
+    kick(c.kq[0]);
     drift(c.nd_f[0]);
   } else if constexpr (INTEG == kRk4) {
     const double z = static_cast<double>(zh) - static_cast<double>(zc);
     const double d = static_cast<double>(dh) - static_cast<double>(dc);
-    const double k1z = c.neg_D * d, k1d = c.A * sin_pi_u(z * s);
+    const double k1z = c.neg_D * d, k1d = scaled_sin(z * s, c.kq[0]);
     const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
-    const double k2z = c.neg_D * d2, k2d = c.A * sin_pi_u(z2 * s);
+    const double k2z = c.neg_D * d2, k2d = scaled_sin(z2 * s, c.kq[0]);
     const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
-    const double k3z = c.neg_D * d3, k3d = c.A * sin_pi_u(z3 * s);
+    const double k3z = c.neg_D * d3, k3d = scaled_sin(z3 * s, c.kq[0]);
     const double z4 = z + k3z, d4 = d + k3d;
-    const double k4z = c.neg_D * d4, k4d = c.A * sin_pi_u(z4 * s);
+    const double k4z = c.neg_D * d4, k4d = scaled_sin(z4 * s, c.kq[0]);
     kahan_add(zh, zc, static_cast<float>((1.0 / 6.0) * ((k1z + 2.0 * k2z) + (2.0 * k3z + k4z))));
     kahan_add(dh, dc, static_cast<float>((1.0 / 6.0) * ((k1d + 2.0 * k2d) + (2.0 * k3d + k4d))));
   }
@@ -330,13 +349,19 @@ __device__ __forceinline__ void run_wave(const BunchDev& b, int64_t w, int turns
 // Kernels
 
 // One bunch; block b covers wave tiles [b * wpb, (b+1) * wpb).
+// LDS doubles per wave for a launch of `turns` turns (the row buffer holds at
+// most kFlushTurns turns of 5 sums).
+__host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
+  return (turns < kFlushTurns ? (turns > 0 ? turns : 1) : kFlushTurns) * 5 * kRowStride;
+}
+
 template <int INTEG, int DT, int P>
 __global__ __launch_bounds__(kMaxBlock) void k_track_single(BunchDev b, int32_t row0) {
   extern __shared__ double lds[];
   const int wib = threadIdx.x >> 6;
   const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wib;
   if (w >= b.waves) return;
-  run_wave<INTEG, DT, P>(b, w, b.turns, row0, lds + wib * kLdsDoublesPerWave);
+  run_wave<INTEG, DT, P>(b, w, b.turns, row0, lds + wib * lds_doubles_per_wave(b.turns));
 }
 
 // Many bunches, one scheme and precision; block -> tiles[blockIdx.x].
@@ -350,7 +375,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_track_tiles(const BunchDev* __res
   const int wib = threadIdx.x >> 6;
   const int64_t w = static_cast<int64_t>(t.wave0) + wib;
   if (w >= b.waves) return;
-  run_wave<INTEG, DT, P>(b, w, turns, row0, lds + wib * kLdsDoublesPerWave);
+  run_wave<INTEG, DT, P>(b, w, turns, row0, lds + wib * lds_doubles_per_wave(turns));
 }
 
 // Engine step: every bunch carries its own scheme, precision and turn count.
@@ -515,8 +540,10 @@ MixedFn pick_mixed(int pi) {
   }
 }
 
-size_t lds_bytes(int block, bool moments) {
-  return moments ? static_cast<size_t>(block / kWave) * kLdsDoublesPerWave * sizeof(double) : 0;
+size_t lds_bytes(int block, bool moments, int turns) {
+  return moments ? static_cast<size_t>(block / kWave) * lds_doubles_per_wave(turns) *
+                       sizeof(double)
+                 : 0;
 }
 
 }  // namespace
@@ -532,7 +559,7 @@ hipError_t launch_track_single(const BunchDev& b, int32_t row0, int ppl, int blo
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(block),
-                     lds_bytes(block, b.partials != nullptr), s, b, row0);
+                     lds_bytes(block, b.partials != nullptr, b.turns), s, b, row0);
   return hipGetLastError();
 }
 
@@ -546,7 +573,7 @@ hipError_t launch_track_tiles(const BunchDev* bunches, const TileDev* tiles, int
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(ntiles)), dim3(block),
-                     lds_bytes(block, moments), s, bunches, tiles, turns, row0);
+                     lds_bytes(block, moments, turns), s, bunches, tiles, turns, row0);
   return hipGetLastError();
 }
 
@@ -557,7 +584,7 @@ hipError_t launch_track_mixed(const BunchDev* bunches, const TileDev* tiles, int
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pick_mixed(pi), dim3(static_cast<unsigned>(ntiles)), dim3(block),
-                     lds_bytes(block, true), s, bunches, tiles);
+                     lds_bytes(block, true, kFlushTurns), s, bunches, tiles);
   return hipGetLastError();
 }
 

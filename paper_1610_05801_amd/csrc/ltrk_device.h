@@ -28,16 +28,18 @@ enum Integrator : int32_t {
 };
 enum DType : int32_t { kF64 = LTRK_F64, kF32C = LTRK_F32C };
 
+// Terms of the polynomial for sin(pi r) / r in r^2 (see sinpi_coeffs.h).
+constexpr int kSinTerms = 9;
+
 // Per-bunch coefficients, derived on the host in FP64 once per call.
 struct Coeffs {
-  double half_rev_per_m;  // s = 2h/C: k z = pi * (s z)
-  double nd[2];           // negated drift weights times D (scheme specific)
-  double kw[2];           // kick weights times A (scheme specific)
-  double neg_D;           // -D (RK4 field)
-  double A;               // A (RK4 field)
-  float nd_f[2];          // nd rounded to FP32, for F32C drift increments
-  float neg_D_f;
-  float pad;
+  double half_rev_per_m;       // s = 2h/C: k z = pi * (s z)
+  double nd[2];                // negated drift weights times D (scheme specific)
+  double kq[2][kSinTerms];     // kick weight x A x the sin(pi r)/r polynomial: a kick is
+                               // delta += r * sum_j kq[j] r^2j (scheme specific; RK4: kq[0]
+                               // carries A)
+  double neg_D;                // -D (RK4 field)
+  float nd_f[2];               // nd rounded to FP32, for F32C drift increments
 };
 
 // One bunch as the kernels see it.

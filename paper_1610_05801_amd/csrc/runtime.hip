@@ -21,6 +21,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "sinpi_coeffs.h"
 
 namespace ltrk {
 
@@ -106,31 +107,31 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
   std::memset(c, 0, sizeof(*c));
   c->half_rev_per_m = 2.0 * r.harmonic / r.circumference_m;
   c->neg_D = -D;
-  c->A = A;
+  double kw[2] = {A, 0.0};  // kick weights x A
   switch (integrator) {
     case LTRK_EULER_CROMER:
       c->nd[0] = -D;
-      c->kw[0] = A;
       break;
     case LTRK_LEAPFROG:
       c->nd[0] = -(0.5 * D);
-      c->kw[0] = A;
       break;
     case LTRK_RUTH4: {
       // Forest-Ruth: drifts th/2, (1-th)/2, (1-th)/2, th/2; kicks th, 1-2th, th.
       const double th = 1.0 / (2.0 - std::cbrt(2.0));
       c->nd[0] = -((0.5 * th) * D);
       c->nd[1] = -((0.5 * (1.0 - th)) * D);
-      c->kw[0] = th * A;
-      c->kw[1] = (1.0 - 2.0 * th) * A;
+      kw[0] = th * A;
+      kw[1] = (1.0 - 2.0 * th) * A;
       break;
     }
-    default:
+    default:  // RK4: the force A sin(k z)
       break;
   }
+  static_assert(kSinTerms == kSinPiTerms, "polynomial length");
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < kSinTerms; ++j) c->kq[i][j] = kw[i] * kSinPiCoeff[j];
   c->nd_f[0] = static_cast<float>(c->nd[0]);
   c->nd_f[1] = static_cast<float>(c->nd[1]);
-  c->neg_D_f = static_cast<float>(c->neg_D);
 }
 
 int64_t waves_for(int64_t n, int ppl) {
@@ -150,10 +151,11 @@ int check_device_range(const void* p, size_t bytes, const char* name) {
   hipError_t e = hipPointerGetAttributes(&attr, p);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return fail(LTRK_EINVAL, "%s is not device memory", name);
+    return fail(LTRK_EINVAL, "%s (%p) is not device memory (%s)", name, p, hipGetErrorString(e));
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
-    return fail(LTRK_EINVAL, "%s is not device memory", name);
+    return fail(LTRK_EINVAL, "%s (%p) is not device memory (memory type %d)", name, p,
+                static_cast<int>(attr.type));
   hipDeviceptr_t base = nullptr;
   size_t size = 0;
   e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
