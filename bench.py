@@ -538,8 +538,8 @@ def summarize_counters(fetch_csv, write_csv, out_path, ppl):
     def pick(d, key):
         return [v for k, vs in d.items() if key(k) for _, v in sorted(vs)]
 
-    cal_f = pick(fetch, lambda k: "mul" in k.lower() or "elementwise" in k.lower())
-    cal_w = pick(write, lambda k: "mul" in k.lower() or "elementwise" in k.lower())
+    cal_f = pick(fetch, lambda k: "MulFunctor" in k)
+    cal_w = pick(write, lambda k: "MulFunctor" in k)
     fus_f = pick(fetch, lambda k: "k_track_single" in k)
     fus_w = pick(write, lambda k: "k_track_single" in k)
     kib = COUNTER_CAL_BYTES / 1024.0

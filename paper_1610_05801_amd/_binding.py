@@ -12,7 +12,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libltrk.so")
+# LTRK_LIBRARY may name another build of the same library (kernel variants).
+LIB_PATH = os.environ.get("LTRK_LIBRARY") or os.path.join(HERE, "libltrk.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libltrk.so is not built: run `python -m paper_1610_05801_amd.build` "
@@ -409,7 +410,7 @@ class Engine:
         z, dp = np.empty(n, t), np.empty(n, t)
         zc = np.empty(n, t) if dt == 1 else None
         dc = np.empty(n, t) if dt == 1 else None
-        mom = np.empty((turns, 5))
+        mom = np.full((turns, 5), np.nan)   # rows a cancelled job never reached stay NaN
         _check(_lib.ltrk_engine_result(self._h, int(slot), z.ctypes.data, dp.ctypes.data,
                                        zc.ctypes.data if zc is not None else None,
                                        dc.ctypes.data if dc is not None else None,

@@ -209,18 +209,19 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
   int rc = with_device(e);
   if (rc) return rc;
   std::vector<int> act;
-  int64_t waves_total = 0;
+  int64_t cols_total = 0, max_groups = 1;
   for (int i = 0; i < static_cast<int>(e->slots.size()); ++i) {
     const Slot& s = e->slots[i];
     if (s.used && !s.cancelled && s.done_turns < s.turns) {
       act.push_back(i);
-      waves_total += s.waves;
+      cols_total += scratch_cols(s.waves);
+      max_groups = std::max(max_groups, finalize_groups(s.waves));
     }
   }
   if (act.empty()) return LTRK_OK;
   // turns this step: bounded by the partial-sum scratch
   int64_t kcap = static_cast<int64_t>(e->partial_bytes / (sizeof(double) * 5)) /
-                 std::max<int64_t>(waves_total, 1);
+                 std::max<int64_t>(cols_total, 1);
   if (kcap < 1) return fail(LTRK_ENOMEM, "engine partial scratch too small for active jobs");
   const int64_t kk = std::min<int64_t>(k, kcap);
   size_t ntiles = 0;
@@ -268,11 +269,13 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
     FinalizeDev& f = hf[j];
     std::memset(&f, 0, sizeof(f));
     f.partials = d.partials;
+    f.stage = d.partials + rows * 5 * s.waves;
     f.waves = s.waves;
+    f.groups = finalize_groups(s.waves);
     f.n = s.n;
     f.out = s.mom + s.done_turns;
     f.rows = static_cast<int32_t>(rows);
-    off += static_cast<size_t>(rows) * 5 * s.waves;
+    off += static_cast<size_t>(rows) * 5 * scratch_cols(s.waves);
     max_rows = std::max<int32_t>(max_rows, static_cast<int32_t>(rows));
     for (int64_t w0 = 0; w0 < s.waves; w0 += wpb) ht[t++] = TileDev{static_cast<int32_t>(j), static_cast<int32_t>(w0)};
     pt += s.n * rows;
@@ -288,7 +291,7 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
   timing_end(e->stream, tok);
   if (er != hipSuccess) return fail_hip(er, "engine track launch");
   timing_begin(e->stream, kTimeFinalize, &tok);
-  er = launch_finalize_multi(e->d_f[b], nb, max_rows, 0, e->stream);
+  er = launch_finalize_multi(e->d_f[b], nb, max_rows, 0, max_groups, e->stream);
   timing_end(e->stream, tok);
   if (er != hipSuccess) return fail_hip(er, "engine finalize launch");
   hipEventRecord(e->buf_ev[b], e->stream);

@@ -29,6 +29,8 @@ bool valid_dtype(int dtype);
 int check_device_range(const void* p, size_t bytes, const char* name);
 
 int64_t waves_for(int64_t n, int ppl);
+// Moment scratch doubles per (row, moment) for W wave tiles (two-stage aware).
+int64_t scratch_cols(int64_t W);
 
 // Current device (for per-device contexts).
 int current_device(int* dev);

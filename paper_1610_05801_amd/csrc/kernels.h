@@ -18,10 +18,13 @@ hipError_t launch_track_tiles(const BunchDev* bunches, const TileDev* tiles, int
 // Tiled launch where every bunch has its own scheme, precision and turn count.
 hipError_t launch_track_mixed(const BunchDev* bunches, const TileDev* tiles, int64_t ntiles,
                               int ppl, int block, hipStream_t s);
+// Moment rows of one bunch (two-stage when f.groups > 1; f.stage then holds
+// rows * 5 * groups doubles).
 hipError_t launch_finalize_single(const FinalizeDev& f, hipStream_t s);
-// Rows [0, rows) of every bunch (bounded by each f.rows) into f.out[out_row0 + row].
+// Rows [0, rows) of every bunch (bounded by each f.rows) into f.out[out_row0 + row];
+// max_groups is the largest f.groups in the table (two-stage reduction when > 1).
 hipError_t launch_finalize_multi(const FinalizeDev* fs, int nf, int rows, int64_t out_row0,
-                                 hipStream_t s);
+                                 int64_t max_groups, hipStream_t s);
 hipError_t launch_fill_nan(ltrk_moments* out, int64_t rows, hipStream_t s);
 hipError_t launch_fill_probe(double* z, double* dp, int64_t n, hipStream_t s);
 

@@ -120,7 +120,9 @@ __device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) 
 
 // ---------------------------------------------------------------------------
 // One turn, FP32 + Kahan state. Drift increments are FP32 products of the FP32
-// momentum value; kick increments are FP64 (phase from the FP64 value
+// momentum value with the drift coefficient carried as an FP32 hi + lo pair (a
+// coefficient rounded to FP32 alone would shift the synchrotron tune by up to
+// 2^-25 relative, a systematic phase error); kick increments are FP64 (phase from the FP64 value
 // hi - comp, sin in FP64) rounded once to FP32. RK4 evaluates its stages in
 // FP64 from the FP64 state value and adds FP32-rounded increments.
 
@@ -128,7 +130,10 @@ template <int INTEG>
 __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float& dc,
                                           const Coeffs& c) {
   const double s = c.half_rev_per_m;
-  auto drift = [&](float ndf) { kahan_add(zh, zc, ndf * (dh - dc)); };
+  auto drift = [&](const float* ndf) {
+    const float v = dh - dc;
+    kahan_add(zh, zc, __builtin_fmaf(ndf[0], v, ndf[1] * v));
+  };
   auto kick = [&](const double* q) {
     const double zv = static_cast<double>(zh) - static_cast<double>(zc);
     kahan_add(dh, dc, static_cast<float>(scaled_sin(zv * s, q)));
@@ -195,32 +200,37 @@ __device__ __forceinline__ void stage_sums(double* buf, int j, const Sums& s, in
 }
 
 // Reduce `rows` staged LDS rows of 64 lane values each; row r goes to
-// out[r * stride]. Row r is summed by the 4 lanes r, r+16, r+32, r+48 over 16
-// values each (pairwise tree), then combined as (q0 + q1) + (q2 + q3).
+// out[r * stride]. Row r is summed by kLanesPerRow lanes (r, r + R, r + 2R, ...
+// with R = 64 / kLanesPerRow), each adding its 64 / kLanesPerRow consecutive
+// values in a pairwise tree; the partial sums are then combined by xor
+// shuffles over R, 2R, ..., which gives every lane of the row the same total.
 __device__ __forceinline__ void flush_rows(const double* buf, int rows, double* out,
                                            int64_t stride, int lane) {
-  const int row = lane & 15;
-  const int quarter = lane >> 4;
-  double part = 0.0;
+  constexpr int R = kWave / kLanesPerRow;   // row slots per flush
+  constexpr int V = kWave / kLanesPerRow;   // values per lane
+  static_assert(kFlushTurns * 5 <= R, "flush rows exceed row slots");
+  const int row = lane & (R - 1);
+  const int part = lane / R;
+  double part_sum = 0.0;
   if (row < rows) {
-    const double2* src = reinterpret_cast<const double2*>(buf + row * kRowStride + quarter * 16);
-    double q[8];
+    const double2* src = reinterpret_cast<const double2*>(buf + row * kRowStride + part * V);
+    double q[V / 2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < V / 2; ++j) {
       const double2 v = src[j];
       q[j] = v.x + v.y;
     }
-    q[0] = q[0] + q[1];
-    q[2] = q[2] + q[3];
-    q[4] = q[4] + q[5];
-    q[6] = q[6] + q[7];
-    q[0] = q[0] + q[2];
-    q[4] = q[4] + q[6];
-    part = q[0] + q[4];
+#pragma unroll
+    for (int w = V / 4; w >= 1; w >>= 1) {
+#pragma unroll
+      for (int j = 0; j < w; ++j) q[j] = q[2 * j] + q[2 * j + 1];
+    }
+    part_sum = q[0];
   }
-  double x = part + __shfl_xor(part, 16);
-  x = x + __shfl_xor(x, 32);
-  if (quarter == 0 && row < rows) out[static_cast<int64_t>(row) * stride] = x;
+  double x = part_sum;
+#pragma unroll
+  for (int off = R; off < kWave; off <<= 1) x = x + __shfl_xor(x, off);
+  if (part == 0 && row < rows) out[static_cast<int64_t>(row) * stride] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -403,17 +413,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_track_mixed(const BunchDev* __res
   }
 }
 
-// Moments of rows of per-wave sums. One wave per row: lane l adds waves
+// Moments of rows of per-wave sums. One wave per row: lane l adds columns
 // l, l + 64, ... in order, then a xor butterfly over the 64 lanes (every lane
-// ends with the same, fixed-order total).
-__device__ __forceinline__ void finalize_row(const FinalizeDev& f, int row) {
+// ends with the same, fixed-order total). `cols` are wave tiles (one stage)
+// or group sums (second stage).
+__device__ __forceinline__ void finalize_row(const double* __restrict__ base, int64_t cols,
+                                             int64_t n, ltrk_moments* out, int row) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t W = f.waves;
-  const double* p = f.partials + static_cast<int64_t>(row) * 5 * W;
+  const double* p = base + static_cast<int64_t>(row) * 5 * cols;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t w = lane; w < W; w += kWave) {
+  for (int64_t w = lane; w < cols; w += kWave) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) s[m] += p[m * W + w];
+    for (int m = 0; m < 5; ++m) s[m] += p[m * cols + w];
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -421,7 +432,7 @@ __device__ __forceinline__ void finalize_row(const FinalizeDev& f, int row) {
     for (int m = 0; m < 5; ++m) s[m] += __shfl_xor(s[m], off);
   }
   if (lane == 0) {
-    const double nd = static_cast<double>(f.n);
+    const double nd = static_cast<double>(n);
     const double mz = s[0] / nd;
     const double md = s[2] / nd;
     double vz = s[1] / nd - mz * mz;
@@ -436,24 +447,78 @@ __device__ __forceinline__ void finalize_row(const FinalizeDev& f, int row) {
     o.mean_dp = md;
     o.rms_dp = __builtin_sqrt(vd);
     o.emit_rms = __builtin_sqrt(e2 > 0.0 ? e2 : 0.0);
-    f.out[row] = o;
+    out[row] = o;
   }
+}
+
+// First stage for bunches with more than kGroupWaves wave tiles: a block of
+// 256 threads adds the per-wave sums of one (row, group) — thread t takes
+// tiles t, t + 256, ... of the group in order, then a xor butterfly per wave
+// and the 4 wave totals in a fixed pairwise order.
+__device__ __forceinline__ void group_sum(const FinalizeDev& f, int row, int64_t g) {
+  __shared__ double red[4][5];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid >> 6;
+  const int64_t W = f.waves;
+  const double* p = f.partials + static_cast<int64_t>(row) * 5 * W;
+  const int64_t w0 = g * kGroupWaves;
+  const int64_t w1 = w0 + kGroupWaves < W ? w0 + kGroupWaves : W;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t w = w0 + tid; w < w1; w += 256) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] += p[m * W + w];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] += __shfl_xor(s[m], off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) red[wave][m] = s[m];
+  }
+  __syncthreads();
+  if (tid < 5)
+    f.stage[(static_cast<int64_t>(row) * 5 + tid) * f.groups + g] =
+        (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+__global__ __launch_bounds__(256) void k_group_single(FinalizeDev f) {
+  group_sum(f, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_group_multi(const FinalizeDev* __restrict__ fs,
+                                                     int32_t rows) {
+  const FinalizeDev f = fs[blockIdx.z];
+  const int row = blockIdx.y;
+  if (f.out == nullptr || f.groups <= 1 || row >= rows || row >= f.rows ||
+      static_cast<int64_t>(blockIdx.x) >= f.groups)
+    return;
+  group_sum(f, row, blockIdx.x);
+}
+
+__device__ __forceinline__ void finalize_bunch_row(const FinalizeDev& f, ltrk_moments* out,
+                                                   int row) {
+  if (f.groups > 1)
+    finalize_row(f.stage, f.groups, f.n, out, row);
+  else
+    finalize_row(f.partials, f.waves, f.n, out, row);
 }
 
 __global__ __launch_bounds__(256) void k_finalize_single(FinalizeDev f) {
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row < f.rows) finalize_row(f, row);
+  if (row < f.rows) finalize_bunch_row(f, f.out, row);
 }
 
 // blockIdx.y selects the bunch; rows [0, min(rows, f.rows)) are reduced and
 // written to f.out[out_row0 + row].
 __global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeDev* __restrict__ fs,
                                                         int32_t rows, int64_t out_row0) {
-  FinalizeDev f = fs[blockIdx.y];
+  const FinalizeDev f = fs[blockIdx.y];
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (f.out == nullptr || row >= rows || row >= f.rows) return;
-  f.out += out_row0;
-  finalize_row(f, row);
+  finalize_bunch_row(f, f.out + out_row0, row);
 }
 
 __global__ void k_fill_nan(ltrk_moments* out, int64_t rows) {
@@ -590,15 +655,29 @@ hipError_t launch_track_mixed(const BunchDev* bunches, const TileDev* tiles, int
 
 hipError_t launch_finalize_single(const FinalizeDev& f, hipStream_t s) {
   if (f.rows <= 0) return hipSuccess;
+  if (f.groups > 1) {
+    if (f.rows > 65535 || f.groups > 0x7fffffff || !f.stage) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_group_single, dim3(static_cast<unsigned>(f.groups), f.rows), dim3(256),
+                       0, s, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int blocks = (f.rows + 3) / 4;
   hipLaunchKernelGGL(k_finalize_single, dim3(blocks), dim3(256), 0, s, f);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_multi(const FinalizeDev* fs, int nf, int rows, int64_t out_row0,
-                                 hipStream_t s) {
+                                 int64_t max_groups, hipStream_t s) {
   if (nf <= 0 || rows <= 0) return hipSuccess;
   if (nf > 65535) return hipErrorInvalidValue;
+  if (max_groups > 1) {
+    if (rows > 65535 || max_groups > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_group_multi, dim3(static_cast<unsigned>(max_groups), rows, nf),
+                       dim3(256), 0, s, fs, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int blocks = (rows + 3) / 4;
   hipLaunchKernelGGL(k_finalize_multi, dim3(blocks, nf), dim3(256), 0, s, fs, rows, out_row0);
   return hipGetLastError();

@@ -39,7 +39,8 @@ struct Coeffs {
                                // delta += r * sum_j kq[j] r^2j (scheme specific; RK4: kq[0]
                                // carries A)
   double neg_D;                // -D (RK4 field)
-  float nd_f[2];               // nd rounded to FP32, for F32C drift increments
+  float nd_f[2][2];            // nd split into FP32 hi + lo (F32C drift increments:
+                               // fma(hi, v, lo * v) carries the coefficient to ~2^-48)
 };
 
 // One bunch as the kernels see it.
@@ -66,10 +67,21 @@ struct TileDev {
   int32_t wave0;
 };
 
+// Per-wave partial sums are added over wave tiles in groups of kGroupWaves;
+// a bunch with more wave tiles than that is reduced in two stages (groups,
+// then the group sums), so the order depends only on the number of tiles.
+constexpr int kGroupWaves = 2048;
+
+__host__ __device__ inline int64_t finalize_groups(int64_t waves) {
+  return waves <= kGroupWaves ? 1 : (waves + kGroupWaves - 1) / kGroupWaves;
+}
+
 // Finalize work: reduce rows of per-wave partial sums of one bunch.
 struct FinalizeDev {
-  const double* partials;
+  const double* partials;  // [rows][5][waves]
+  double* stage;           // [rows][5][groups] group sums when groups > 1
   int64_t waves;
+  int64_t groups;
   int64_t n;
   ltrk_moments* out;
   int32_t rows;

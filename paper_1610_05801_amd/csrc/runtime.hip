@@ -130,8 +130,17 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
   static_assert(kSinTerms == kSinPiTerms, "polynomial length");
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < kSinTerms; ++j) c->kq[i][j] = kw[i] * kSinPiCoeff[j];
-  c->nd_f[0] = static_cast<float>(c->nd[0]);
-  c->nd_f[1] = static_cast<float>(c->nd[1]);
+  for (int i = 0; i < 2; ++i) {
+    c->nd_f[i][0] = static_cast<float>(c->nd[i]);
+    c->nd_f[i][1] = static_cast<float>(c->nd[i] - static_cast<double>(c->nd_f[i][0]));
+  }
+}
+
+// Doubles per (row, moment) of moment scratch for a bunch of W wave tiles:
+// the per-wave sums plus, for two-stage finalizes, the group sums.
+int64_t scratch_cols(int64_t W) {
+  const int64_t G = finalize_groups(W);
+  return W + (G > 1 ? G : 0);
 }
 
 int64_t waves_for(int64_t n, int ppl) {
@@ -379,9 +388,10 @@ void key_add(std::string& k, const T& v) {
 
 // Rows (turns) of partial sums per finalize chunk for `waves_total` waves,
 // a multiple of K unless the whole run is shorter.
-int64_t chunk_rows(int64_t turns, int64_t K, int64_t waves_total) {
-  const int64_t per_row = waves_total * 5 * static_cast<int64_t>(sizeof(double));
+int64_t chunk_rows(int64_t turns, int64_t K, int64_t cols_total, bool two_stage) {
+  const int64_t per_row = cols_total * 5 * static_cast<int64_t>(sizeof(double));
   int64_t cap = static_cast<int64_t>(scratch_cap_bytes()) / std::max<int64_t>(per_row, 1);
+  if (two_stage && cap > 65535) cap = 65535;  // grid rows of the group-sum stage
   if (cap >= turns) return turns;
   if (cap >= K) return (cap / K) * K;
   return cap;  // may be < K (the caller then shortens launches)
@@ -440,11 +450,13 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   int64_t K = plan.turns_per_launch;
   int64_t rows = turns;
   void* scratch = nullptr;
+  const int64_t groups = finalize_groups(b.waves);
   if (mom) {
-    rows = chunk_rows(turns, K, b.waves);
+    rows = chunk_rows(turns, K, scratch_cols(b.waves), groups > 1);
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)b.waves);
     K = std::min<int64_t>(K, rows);
-    if ((rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * b.waves * sizeof(double),
+    if ((rc = ensure_scratch(c, s,
+                             static_cast<size_t>(rows) * 5 * scratch_cols(b.waves) * sizeof(double),
                              &scratch)))
       return rc;
   }
@@ -474,7 +486,9 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       FinalizeDev f;
       std::memset(&f, 0, sizeof(f));
       f.partials = static_cast<const double*>(scratch);
+      f.stage = static_cast<double*>(scratch) + rows * 5 * b.waves;
       f.waves = b.waves;
+      f.groups = groups;
       f.n = n;
       f.out = mom + c0;
       f.rows = static_cast<int32_t>(len);
@@ -518,7 +532,8 @@ static int moments_single(const void* z, const void* dp, const void* zc, const v
   DeviceCtx& c = ctx_for(dev);
   std::lock_guard<std::mutex> lock(c.mu);
   void* scratch = nullptr;
-  if ((rc = ensure_scratch(c, s, static_cast<size_t>(5) * b.waves * sizeof(double), &scratch)))
+  if ((rc = ensure_scratch(c, s, static_cast<size_t>(5) * scratch_cols(b.waves) * sizeof(double),
+                           &scratch)))
     return rc;
   b.partials = static_cast<double*>(scratch);
   hipError_t e = launch_track_single(b, 0, ppl, block, s);
@@ -526,7 +541,9 @@ static int moments_single(const void* z, const void* dp, const void* zc, const v
   FinalizeDev f;
   std::memset(&f, 0, sizeof(f));
   f.partials = b.partials;
+  f.stage = b.partials + 5 * b.waves;
   f.waves = b.waves;
+  f.groups = finalize_groups(b.waves);
   f.n = n;
   f.out = out;
   f.rows = 1;
@@ -582,8 +599,9 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
 
   std::vector<BunchDev> bd(nb);
   std::vector<TileDev> tiles;
-  int64_t waves_mom = 0;  // waves of bunches that want moments
-  bool any_mom = false;
+  int64_t waves_mom = 0;  // scratch columns of bunches that want moments
+  bool any_mom = false, two_stage = false;
+  int64_t max_groups = 1;
   for (int i = 0; i < nb; ++i) {
     const ltrk_bunch& in = bunches[i];
     BunchDev& b = bd[i];
@@ -603,14 +621,16 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
       tiles.push_back(TileDev{i, static_cast<int32_t>(w0)});
     }
     if (in.moments && in.n > 0) {
-      waves_mom += b.waves;
+      waves_mom += scratch_cols(b.waves);
       any_mom = true;
+      max_groups = std::max(max_groups, finalize_groups(b.waves));
+      two_stage = two_stage || finalize_groups(b.waves) > 1;
     }
   }
   int64_t K = plan.turns_per_launch;
   int64_t rows = turns;
   if (any_mom) {
-    rows = chunk_rows(turns, K, waves_mom);
+    rows = chunk_rows(turns, K, waves_mom, two_stage);
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)waves_mom);
     K = std::min<int64_t>(K, rows);
   }
@@ -632,12 +652,14 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
       FinalizeDev f;
       std::memset(&f, 0, sizeof(f));
       f.partials = bd[i].partials;
+      f.stage = bd[i].partials + rows * 5 * bd[i].waves;
       f.waves = bd[i].waves;
+      f.groups = finalize_groups(bd[i].waves);
       f.n = bd[i].n;
       f.out = bunches[i].moments;
       f.rows = max_rows;
       fin.push_back(f);
-      off += rows * 5 * bd[i].waves;
+      off += rows * 5 * scratch_cols(bd[i].waves);
     }
   }
 
@@ -702,7 +724,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
     if (nf > 0) {
       const int mr = static_cast<int>(len);
       seq.push_back({kTimeFinalize, [=](hipStream_t st) {
-                       return launch_finalize_multi(d_f, nf, mr, c0, st);
+                       return launch_finalize_multi(d_f, nf, mr, c0, max_groups, st);
                      }});
     }
   }

@@ -2,6 +2,8 @@
 while others run, advanced together step by step; each job's result is
 bitwise equal to tracking it alone with the same particles-per-lane (4), and
 admission respects slots and the arena budget."""
+import time
+
 import numpy as np
 import pytest
 
@@ -114,6 +116,11 @@ def test_engine_admission_limits(ltrk):
         eng.admit(10, 10, SPS_RING, "leapfrog", "f64", z0[:10], dp0[:10])
     for _ in range(10):
         eng.step(50)
+    torch.cuda.synchronize()
+    for _ in range(1000):                         # steps are asynchronous: wait for them
+        if eng.poll(a) and eng.poll(c):
+            break
+        time.sleep(0.001)
     assert eng.poll(a) and eng.poll(c)
     z, dp, mom = eng.result(a)
     z2, dp2, mom2 = eng.result(c)

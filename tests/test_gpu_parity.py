@@ -141,10 +141,26 @@ def test_empty_and_zero_turn_calls(ltrk):
 
 
 def test_rejects_short_buffers(ltrk):
-    z = torch.zeros(100, dtype=torch.float64, device="cuda")
-    mom = torch.zeros((4, 5), dtype=torch.float64, device="cuda")
-    with pytest.raises(ltrk.LtrkError):
-        ltrk.ltrk_track_f64(z, z, 5, SPS_RING, "leapfrog", mom)   # 5 rows needed
+    """The library itself (not the binding) refuses arrays shorter than stated:
+    called through the raw C entry point with n and turns larger than the
+    allocations, it returns EINVAL before enqueueing anything."""
+    import ctypes
+    lib = ltrk._binding._lib
+    ring = ltrk.Ring.of(SPS_RING)
+    buf = torch.zeros(3 << 18, dtype=torch.float64, device="cuda")   # one 6 MiB allocation
+    z = ctypes.c_void_p(buf.data_ptr())
+    dp = ctypes.c_void_p(buf.data_ptr() + 8 * (1 << 18))
+    mom = ctypes.c_void_p(buf.data_ptr() + 8 * (2 << 18))
+    s = ctypes.c_void_p(None)
+    ok = lib.ltrk_track_f64(z, dp, 1 << 18, 1, ctypes.byref(ring), 1, mom, s)
+    assert ok == 0
+    # moments rows past the end of the allocation
+    too_many_rows = (1 << 18) // 5 + 1
+    assert lib.ltrk_track_f64(z, dp, 1 << 18, too_many_rows, ctypes.byref(ring), 1, mom,
+                              s) == ltrk.LTRK_EINVAL
+    # particles past the end of the allocation (dp starts 2 MiB before the end)
+    assert lib.ltrk_track_f64(z, dp, 3 << 18, 1, ctypes.byref(ring), 1, None,
+                              s) == ltrk.LTRK_EINVAL
     torch.cuda.synchronize()
 
 
