@@ -19,7 +19,9 @@
  *   - Arrays named z, dp, z_comp, dp_comp, moments are DEVICE pointers owned
  *     by the caller; the library never frees them. Arrays are contiguous
  *     structure-of-arrays, one element per particle. A pointer that is not
- *     device memory, or whose allocation is shorter than the stated length,
+ *     device memory, or whose device allocation (the hipMalloc block it lies
+ *     in; for sub-allocating allocators such as PyTorch's caching allocator,
+ *     that block is the allocator's segment) ends before the stated length,
  *     is rejected with LTRK_EINVAL before anything is enqueued.
  *   - `stream` is a hipStream_t (NULL = the null stream). Calls are
  *     asynchronous: they return after enqueueing; device faults surface at the

@@ -73,13 +73,16 @@ int log2_bucket(int64_t n) {
 
 ltrk_plan default_plan(int /*integrator*/, int /*dtype*/, int64_t n, bool /*batched*/) {
   ltrk_plan p;
-  p.turns_per_launch = 128;
+  p.turns_per_launch = 512;
   p.block = 256;
   p.use_graph = 1;
-  // Enough wave tiles to give every one of the 1024 SIMDs work: prefer more
-  // particles per lane (ILP, cheaper moment reduction) only when that still
-  // leaves >= 2 waves per SIMD.
-  if (waves_for(n, 4) >= 2048)
+  // More particles per lane give more independent FP64 chains per lane and
+  // spread the per-turn moment reduction over more particles; use them while
+  // the wave tiles still cover the 1024 SIMDs about 1.5 times (measured at
+  // 1e6 particles: P = 8 beats P = 4 by ~15%).
+  if (waves_for(n, 8) >= 1536)
+    p.ppl = 8;
+  else if (waves_for(n, 4) >= 2048)
     p.ppl = 4;
   else if (waves_for(n, 2) >= 2048)
     p.ppl = 2;

@@ -141,27 +141,34 @@ def test_empty_and_zero_turn_calls(ltrk):
 
 
 def test_rejects_short_buffers(ltrk):
-    """The library itself (not the binding) refuses arrays shorter than stated:
-    called through the raw C entry point with n and turns larger than the
-    allocations, it returns EINVAL before enqueueing anything."""
+    """The library itself (not the binding) refuses arrays that run past the
+    end of their device allocation: called through the raw C entry point on
+    one exact 6 MiB hipMalloc allocation with n or turns too large, it returns
+    EINVAL before enqueueing anything. (Tensors from a caching allocator are
+    checked against the allocator's underlying segment instead.)"""
     import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")     # the runtime torch already loaded
     lib = ltrk._binding._lib
     ring = ltrk.Ring.of(SPS_RING)
-    buf = torch.zeros(3 << 18, dtype=torch.float64, device="cuda")   # one 6 MiB allocation
-    z = ctypes.c_void_p(buf.data_ptr())
-    dp = ctypes.c_void_p(buf.data_ptr() + 8 * (1 << 18))
-    mom = ctypes.c_void_p(buf.data_ptr() + 8 * (2 << 18))
-    s = ctypes.c_void_p(None)
-    ok = lib.ltrk_track_f64(z, dp, 1 << 18, 1, ctypes.byref(ring), 1, mom, s)
-    assert ok == 0
-    # moments rows past the end of the allocation
-    too_many_rows = (1 << 18) // 5 + 1
-    assert lib.ltrk_track_f64(z, dp, 1 << 18, too_many_rows, ctypes.byref(ring), 1, mom,
-                              s) == ltrk.LTRK_EINVAL
-    # particles past the end of the allocation (dp starts 2 MiB before the end)
-    assert lib.ltrk_track_f64(z, dp, 3 << 18, 1, ctypes.byref(ring), 1, None,
-                              s) == ltrk.LTRK_EINVAL
-    torch.cuda.synchronize()
+    base = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(base), ctypes.c_size_t(6 << 20)) == 0
+    try:
+        mib = 1 << 20
+        z = ctypes.c_void_p(base.value)
+        dp = ctypes.c_void_p(base.value + 2 * mib)
+        mom = ctypes.c_void_p(base.value + 4 * mib)
+        s = ctypes.c_void_p(None)
+        n = (2 * mib) // 8
+        assert hip.hipMemset(base, 0, ctypes.c_size_t(6 << 20)) == 0
+        assert lib.ltrk_track_f64(z, dp, n, 1, ctypes.byref(ring), 1, mom, s) == 0
+        rows_fit = (2 * mib) // 40
+        assert lib.ltrk_track_f64(z, dp, n, rows_fit + 1, ctypes.byref(ring), 1, mom,
+                                  s) == ltrk.LTRK_EINVAL
+        assert lib.ltrk_track_f64(z, dp, 2 * n + 1, 1, ctypes.byref(ring), 1, None,
+                                  s) == ltrk.LTRK_EINVAL
+        assert hip.hipDeviceSynchronize() == 0
+    finally:
+        hip.hipFree(base)
 
 
 def test_paper_scale_sampled(ltrk):
