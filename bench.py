@@ -178,7 +178,7 @@ def bench_default(args):
         # one launch per turn (HBM-bound form) on the same workload, 1e3 turns
         Tu = min(T, 1000)
         saved = ltrk.ltrk_get_plan(integ, "f64", n)
-        ltrk.ltrk_set_plan(1, plan["block"], plan["ppl"], 1)
+        ltrk.ltrk_set_plan(1, 256, 4, 1)   # HBM-bound form: 4 particles per lane
         z1, d1 = zt.to(dev), dt.to(dev)
         mu = torch.empty((Tu, 5), dtype=torch.float64, device=dev)
         with torch.cuda.stream(stream):
@@ -416,7 +416,8 @@ def bench_batched(args):
                                                               for a in (zh, dh, zc, dc)]
             bunches.append(b)
         with torch.cuda.stream(stream):
-            ltrk.ltrk_track_batched(bunches, 64, "leapfrog", dtype, stream=stream)   # warm-up
+            warm = [dict(b, moments=None) for b in bunches]
+            ltrk.ltrk_track_batched(warm, 64, "leapfrog", dtype, stream=stream)   # warm-up
             stream.synchronize()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -431,49 +432,63 @@ def bench_batched(args):
 
 
 def bench_serving(args):
-    """Poisson request stream through the continuous-batching engine."""
+    """Poisson request stream through the continuous-batching engine: capacity
+    from a saturating run (all requests at t = 0), then open-loop Poisson
+    arrivals at fractions of that capacity; p50/p99 arrival-to-result latency
+    and aggregate particle-turns/s per load."""
     import torch
     import paper_1610_05801_amd as ltrk
     from paper_1610_05801_amd.serve import Request, run_stream
     from synth import gaussian_bunch, request_stream, split_f32c, SPS_RING
     count = args.requests
     budget = int(args.budget_gb * (1 << 30))
-    probe = request_stream(1.0, count)
-    work = np.array([r.n * r.turns for r in probe], dtype=np.float64)
-    # capacity estimate: mean work per request over a measured mixed rate
-    rate_pt = args.capacity_rate
-    capacity = rate_pt / work.mean()
-    log("serving: %d requests, mean work %.3e particle-turns, capacity ~%.2f req/s"
-        % (count, work.mean(), capacity))
-    out = {"workload": "serving: Poisson requests, n log-uniform 1e3-1e7, turns 1e3-1e5, "
-                       "EC/LF/Ruth4 x F64/F32C", "requests": count, "budget_bytes": budget,
-           "capacity_req_per_s_estimate": capacity, "rows": []}
-    for frac in args.load:
-        lam = frac * capacity
-        specs = request_stream(lam, count)
-        reqs = []
-        for sp in specs:
-            r = dict(SPS_RING, voltage_V=sp.voltage_V, harmonic=sp.harmonic)
-            z0, dp0 = gaussian_bunch(sp.n, _matched_sigma_z(ltrk, r, sp.sigma_dp), sp.sigma_dp,
-                                     sp.seed)
-            state = (z0, dp0)
-            if sp.dtype == "f32c":
-                zh, zc = split_f32c(z0)
-                dh, dc = split_f32c(dp0)
-                state = (zh, dh, zc, dc)
-            reqs.append(Request(sp.rid, sp.arrival_s, sp.n, sp.turns, r, sp.integrator,
-                                sp.dtype, state))
+    specs = request_stream(1.0, count)
+    log("serving: generating %d requests" % count)
+    states = {}
+    rings = {}
+    for sp in specs:
+        r = dict(SPS_RING, voltage_V=sp.voltage_V, harmonic=sp.harmonic)
+        z0, dp0 = gaussian_bunch(sp.n, _matched_sigma_z(ltrk, r, sp.sigma_dp), sp.sigma_dp,
+                                 sp.seed)
+        if sp.dtype == "f32c":
+            zh, zc = split_f32c(z0)
+            dh, dc = split_f32c(dp0)
+            states[sp.rid] = (zh, dh, zc, dc)
+        else:
+            states[sp.rid] = (z0, dp0)
+        rings[sp.rid] = r
+    work = np.array([sp.n * sp.turns for sp in specs], dtype=np.float64)
+
+    def requests_at(arrivals):
+        return [Request(sp.rid, float(t), sp.n, sp.turns, rings[sp.rid], sp.integrator,
+                        sp.dtype, states[sp.rid]) for sp, t in zip(specs, arrivals)]
+
+    def run(arrivals):
         eng = ltrk.Engine(budget, max_slots=args.slots)
-        recs, wall = run_stream(eng, reqs, k=args.k)
+        recs, wall = run_stream(eng, requests_at(arrivals), k=args.k)
+        st = eng.stats()
         eng.close()
         lat = np.array([x.latency_s for x in recs])
-        pt = sum(x.n * x.turns for x in recs)
-        row = {"load": frac, "rate_req_per_s": lam, "p50_latency_s": float(np.percentile(lat, 50)),
-               "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
-               "wall_s": wall, "particle_turns_per_s": pt / wall, "completed": len(recs)}
+        return {"p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)),
+                "mean_latency_s": float(lat.mean()), "wall_s": wall,
+                "particle_turns_per_s": float(sum(x.n * x.turns for x in recs)) / wall,
+                "completed": len(recs), "engine_steps": st["steps"]}
+
+    sat = run(np.zeros(count))
+    capacity = sat["particle_turns_per_s"] / work.mean()
+    log("saturated: %s; capacity %.2f req/s" % (json.dumps(sat), capacity))
+    out = {"workload": "serving: Poisson requests, n log-uniform 1e3-1e7, turns log-uniform "
+                       "1e3-1e5, EC/LF/Ruth4 x F64/F32C, matched bunches",
+           "requests": count, "budget_bytes": budget, "slots": args.slots, "k": args.k,
+           "mean_particle_turns_per_request": float(work.mean()),
+           "saturated": sat, "capacity_req_per_s": capacity, "rows": []}
+    for frac in args.load:
+        lam = frac * capacity
+        arrivals = np.array([sp.arrival_s for sp in request_stream(lam, count)])
+        row = dict(run(arrivals), load=frac, rate_req_per_s=lam)
         out["rows"].append(row)
         log(json.dumps(row))
-        del reqs
     print(json.dumps(out), flush=True)
 
 
@@ -581,8 +596,6 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8, 1.0])
-    ap.add_argument("--capacity-rate", type=float, default=6.0e11,
-                    help="particle-turns/s assumed for the capacity estimate")
     ap.add_argument("--summarize", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "PPL"),
                     help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
     args = ap.parse_args()
