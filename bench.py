@@ -33,9 +33,18 @@ METRIC = ("particle-turns/sec, FP64 leap-frog, 10^6 particles; FP32 vs FP64; "
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
+
+
+def _sin_terms() -> int:
+    import re
+    with open(os.path.join(ROOT, "paper_1610_05801_amd", "csrc", "sinpi_coeffs.h")) as f:
+        return int(re.search(r"kSinPiTerms = (\d+);", f.read()).group(1))
+
+
 # Algorithmic FP64 flops per particle-turn (FMA = 2), see the design doc:
-# sin(k z) = phase multiply + reduction subtract + r^2 + 8 FMA + final multiply = 20.
-SIN_FLOPS = 20
+# sin(k z) = phase multiply + reduction subtract + r^2 + (terms - 1) FMA + final
+# multiply by r.
+SIN_FLOPS = 4 + 2 * (_sin_terms() - 1)
 FLOPS_PER_PT = {
     "euler_cromer": 2 + 2 + SIN_FLOPS + 8,
     "leapfrog": 4 + 2 + SIN_FLOPS + 8,

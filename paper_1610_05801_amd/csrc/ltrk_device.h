@@ -29,7 +29,7 @@ enum Integrator : int32_t {
 enum DType : int32_t { kF64 = LTRK_F64, kF32C = LTRK_F32C };
 
 // Terms of the polynomial for sin(pi r) / r in r^2 (see sinpi_coeffs.h).
-constexpr int kSinTerms = 9;
+constexpr int kSinTerms = 8;
 
 // Per-bunch coefficients, derived on the host in FP64 once per call.
 struct Coeffs {
