@@ -9,7 +9,10 @@
 // Layout and mapping (MI355X-first):
 //   - state is structure-of-arrays in HBM; a wave tile owns 64 * P
 //     consecutive particles, lane l holding particles tile + p*64 + l, so each
-//     load/store instruction moves 64 consecutive elements;
+//     load/store instruction moves 64 consecutive elements; the state is read
+//     and written with nontemporal hints (it streams: each element is touched
+//     once per launch; measured +12% HBM throughput for one launch per turn
+//     at 2.5e8 particles);
 //   - P particles per lane give P independent dependency chains per lane
 //     (ILP for the FP64 VALU, which is the bound once turns are fused);
 //   - per-turn moment sums: each lane sums its P particles, the 5 lane sums
@@ -250,8 +253,8 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, int64_t w, int turns
     z[p] = 0.0;
     d[p] = 0.0;
     if (i < b.n) {
-      z[p] = zp[i];
-      d[p] = dpp[i];
+      z[p] = __builtin_nontemporal_load(&zp[i]);
+      d[p] = __builtin_nontemporal_load(&dpp[i]);
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
@@ -277,8 +280,8 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, int64_t w, int turns
     for (int p = 0; p < P; ++p) {
       const int64_t i = first + static_cast<int64_t>(p) * kWave;
       if (i < b.n) {
-        zp[i] = z[p];
-        dpp[i] = d[p];
+        __builtin_nontemporal_store(z[p], &zp[i]);
+        __builtin_nontemporal_store(d[p], &dpp[i]);
       }
     }
   }
@@ -299,10 +302,10 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
     const int64_t i = first + static_cast<int64_t>(p) * kWave;
     zh[p] = zc[p] = dh[p] = dc[p] = 0.0f;
     if (i < b.n) {
-      zh[p] = zp[i];
-      zc[p] = zcp[i];
-      dh[p] = dpp[i];
-      dc[p] = dcp[i];
+      zh[p] = __builtin_nontemporal_load(&zp[i]);
+      zc[p] = __builtin_nontemporal_load(&zcp[i]);
+      dh[p] = __builtin_nontemporal_load(&dpp[i]);
+      dc[p] = __builtin_nontemporal_load(&dcp[i]);
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
@@ -330,10 +333,10 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
     for (int p = 0; p < P; ++p) {
       const int64_t i = first + static_cast<int64_t>(p) * kWave;
       if (i < b.n) {
-        zp[i] = zh[p];
-        zcp[i] = zc[p];
-        dpp[i] = dh[p];
-        dcp[i] = dc[p];
+        __builtin_nontemporal_store(zh[p], &zp[i]);
+        __builtin_nontemporal_store(zc[p], &zcp[i]);
+        __builtin_nontemporal_store(dh[p], &dpp[i]);
+        __builtin_nontemporal_store(dc[p], &dcp[i]);
       }
     }
   }
