@@ -507,8 +507,8 @@ COUNTER_CAL_BYTES = 1 << 29   # 512 MiB read + 512 MiB written by the calibratio
 def bench_counters(args):
     """Kernels for rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, SQ_*): a
     calibration multiply-by-one of known size, the fused leap-frog kernel at
-    1e6 particles (K = 128, 4 launches) and the one-launch-per-turn kernel at
-    1e8 particles (5 turns)."""
+    1e6 particles with the benchmark's plan (4 launches) and the
+    one-launch-per-turn kernel at 1e8 particles (5 turns)."""
     import torch
     import paper_1610_05801_amd as ltrk
     from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch
@@ -522,10 +522,11 @@ def bench_counters(args):
     n = 1_000_000
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
     z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
-    plan = ltrk.ltrk_get_plan("leapfrog", "f64", n)
-    ltrk.ltrk_set_plan(128, plan["block"], plan["ppl"], 0)
-    mom = torch.empty((512, 5), dtype=torch.float64, device=dev)
-    ltrk.ltrk_track_f64(z, dp, 512, SPS_RING, "leapfrog", mom)
+    plan = ltrk.ltrk_get_plan("leapfrog", "f64", n)   # the benchmark's plan
+    K = plan["turns_per_launch"]
+    ltrk.ltrk_set_plan(K, plan["block"], plan["ppl"], 0)
+    mom = torch.empty((4 * K, 5), dtype=torch.float64, device=dev)
+    ltrk.ltrk_track_f64(z, dp, 4 * K, SPS_RING, "leapfrog", mom)
     torch.cuda.synchronize()
     n2 = 100_000_000
     g = torch.Generator(device=dev).manual_seed(7)
@@ -536,11 +537,11 @@ def bench_counters(args):
     ltrk.ltrk_track_f64(z2, d2, 5, SPS_RING, "leapfrog", mom2)
     torch.cuda.synchronize()
     ltrk.ltrk_set_plan()
-    print(json.dumps({"workload": "counters", "fused_plan": dict(plan, turns_per_launch=128),
+    print(json.dumps({"workload": "counters", "fused_plan": plan,
                       "calibration_bytes": COUNTER_CAL_BYTES}), flush=True)
 
 
-def summarize_counters(fetch_csv, write_csv, out_path, ppl):
+def summarize_counters(fetch_csv, write_csv, out_path, turns_per_launch):
     """Condense two rocprofv3 --pmc CSVs (FETCH_SIZE run, WRITE_SIZE run) into
     HBM bytes per particle-turn for the fused and unfused kernels, scaled by
     what the same counters read for the calibration kernel."""
@@ -569,15 +570,17 @@ def summarize_counters(fetch_csv, write_csv, out_path, ppl):
     kib = COUNTER_CAL_BYTES / 1024.0
     f_scale = kib / np.median(cal_f)
     w_scale = kib / np.median(cal_w)
-    # k_track_single dispatches: 4 fused (1e6 x 128 turns) then 5 unfused (1e8 x 1 turn)
+    # k_track_single dispatches: 4 fused (1e6 x K turns) then 5 unfused (1e8 x 1 turn)
+    K = float(turns_per_launch)
     fused = {"fetch_bytes": float(np.median(fus_f[:4])) * 1024 * f_scale,
-             "write_bytes": float(np.median(fus_w[:4])) * 1024 * w_scale, "particle_turns": 1e6 * 128}
+             "write_bytes": float(np.median(fus_w[:4])) * 1024 * w_scale,
+             "particle_turns": 1e6 * K, "turns_per_launch": K}
     unfused = {"fetch_bytes": float(np.median(fus_f[4:])) * 1024 * f_scale,
                "write_bytes": float(np.median(fus_w[4:])) * 1024 * w_scale, "particle_turns": 1e8}
-    out = {"kernel_hash": kernel_source_hash(), "ppl": ppl,
+    out = {"kernel_hash": kernel_source_hash(),
            "calibration": {"bytes_each_way": COUNTER_CAL_BYTES, "fetch_scale": f_scale,
                            "write_scale": w_scale},
-           "fused_leapfrog_1e6_K128": fused, "unfused_leapfrog_1e8": unfused,
+           "fused_leapfrog_1e6": fused, "unfused_leapfrog_1e8": unfused,
            "hbm_bytes_per_particle_turn": (fused["fetch_bytes"] + fused["write_bytes"]) / fused["particle_turns"],
            "unfused_hbm_bytes_per_particle_turn":
                (unfused["fetch_bytes"] + unfused["write_bytes"]) / unfused["particle_turns"]}
@@ -605,7 +608,7 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8, 1.0])
-    ap.add_argument("--summarize", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "PPL"),
+    ap.add_argument("--summarize", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "K"),
                     help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
