@@ -391,6 +391,40 @@ def bench_precision(args):
                       "subset": int(idx.size), "results": results}), flush=True)
 
 
+def bench_schemes(args):
+    """Every scheme in FP64 and F32C at 1e6 particles x 2048 turns, moments
+    every turn, default plans; kernel time from HIP events."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch, split_f32c
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n, T = args.particles, 2048
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    zh, zc = split_f32c(z0)
+    dh, dc = split_f32c(dp0)
+    mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+    rows = []
+    for integ in ("euler_cromer", "leapfrog", "ruth4", "rk4"):
+        for dtype in ("f64", "f32c"):
+            if dtype == "f64":
+                arrays = (torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev))
+            else:
+                arrays = tuple(torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc))
+            dt, tm = _timed_track(ltrk, torch, stream, n, T, integ, dtype, arrays, mom)
+            kern = tm["track_ms"] / max(tm["track_launches"], 1)
+            per_launch = n * T / max(tm["track_launches"], 1)
+            row = {"integrator": integ, "dtype": dtype, "particle_turns_per_s": n * T / dt,
+                   "kernel_particle_turns_per_s": per_launch / (kern * 1e-3),
+                   "flops_per_particle_turn": FLOPS_PER_PT[integ],
+                   "kernel_tflops": FLOPS_PER_PT[integ] * per_launch / (kern * 1e-3) / 1e12,
+                   "plan": ltrk.ltrk_get_plan(integ, dtype, n)}
+            rows.append(row)
+            log(json.dumps(row))
+    print(json.dumps({"workload": "schemes: %d particles x %d turns" % (n, T), "rows": rows}),
+          flush=True)
+
+
 def _matched_sigma_z(ltrk, ring, sigma_dp):
     d = ltrk.ltrk_derive(ring)
     return sigma_dp * d["slip_length"] / d["omega_s"]
@@ -596,7 +630,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
-                             "counters"])
+                             "counters", "schemes"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
@@ -622,7 +656,7 @@ def main():
         return
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
-     "counters": bench_counters}[args.workload](args)
+     "counters": bench_counters, "schemes": bench_schemes}[args.workload](args)
 
 
 if __name__ == "__main__":
