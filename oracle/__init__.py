@@ -64,6 +64,9 @@ def _load():
             lib.oracle_track.restype = ctypes.c_int
             lib.oracle_moments.argtypes = [p, p, ctypes.c_int64, p]
             lib.oracle_moments.restype = None
+            lib.oracle_track_rf2.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + [d] * 13 + \
+                [ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
+            lib.oracle_track_rf2.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -132,6 +135,51 @@ def hamiltonian(z, dp, ring) -> np.ndarray:
     z = np.asarray(z, dtype=np.float64)
     dp = np.asarray(dp, dtype=np.float64)
     return -0.5 * c["D"] * dp * dp + (c["A"] / c["k"]) * (np.cos(c["k"] * z) - 1.0)
+
+
+RF2_FIELDS = ("phi1_rad", "harmonic2", "voltage2_V", "phi2_rad", "eta1", "eta2")
+
+
+def _rf2_values(rf2) -> list:
+    get = (lambda k: rf2[k]) if isinstance(rf2, dict) else (lambda k: getattr(rf2, k))
+    return [float(get(k)) for k in RF2_FIELDS]
+
+
+def track_rf2(z, dp, turns: int, rf2, integrator="leapfrog", substeps: int = 1,
+              with_moments: bool = True, threads: int = 0):
+    """Track copies of (z, dp) through the extended map (double-harmonic RF
+    with phase offsets, slip factor eta0 + eta1 dp + eta2 dp^2). `rf2` holds
+    the ring fields plus phi1_rad, harmonic2, voltage2_V, phi2_rad, eta1, eta2."""
+    integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    z = np.array(z, dtype=np.float64, copy=True, order="C").ravel()
+    dp = np.array(dp, dtype=np.float64, copy=True, order="C").ravel()
+    if z.shape != dp.shape:
+        raise ValueError("z and dp differ in length")
+    mom = np.empty((max(turns, 0), 5)) if with_moments else None
+    rc = _load().oracle_track_rf2(_ptr(z), _ptr(dp), z.size, int(turns), *_ring_values(rf2),
+                                  *_rf2_values(rf2), integ, int(substeps),
+                                  _ptr(mom) if mom is not None else None, int(threads))
+    if rc != 0:
+        raise ValueError("invalid arguments to oracle_track_rf2")
+    return z, dp, mom
+
+
+def hamiltonian_rf2(z, dp, rf2) -> np.ndarray:
+    """H = -C (eta0 dp^2/2 + eta1 dp^3/3 + eta2 dp^4/4) + sum_i (A_i/k_i) cos(k_i z + phi_i),
+    whose flow is the extended map's vector field."""
+    c = derive(rf2)
+    get = (lambda k: rf2[k]) if isinstance(rf2, dict) else (lambda k: getattr(rf2, k))
+    C = float(get("circumference_m"))
+    eta1, eta2 = float(get("eta1")), float(get("eta2"))
+    A2 = float(get("charge_e")) * float(get("voltage2_V")) / (c["beta"] * float(get("p0c_eV")))
+    k2 = 2.0 * np.pi * float(get("harmonic2")) / C
+    z = np.asarray(z, dtype=np.float64)
+    dp = np.asarray(dp, dtype=np.float64)
+    h = -C * (c["eta"] * dp ** 2 / 2 + eta1 * dp ** 3 / 3 + eta2 * dp ** 4 / 4)
+    h = h + (c["A"] / c["k"]) * np.cos(c["k"] * z + float(get("phi1_rad")))
+    if A2 != 0.0:
+        h = h + (A2 / k2) * np.cos(k2 * z + float(get("phi2_rad")))
+    return h
 
 
 def max_threads() -> int:

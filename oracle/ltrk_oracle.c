@@ -283,6 +283,129 @@ int oracle_track(double *z, double *dp, int64_t n, int64_t turns, double C, doub
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Extended map: double-harmonic RF with phase offsets and a slip factor
+ * expanded in delta. The paper's hollow-bunch run applies two RF kicks and
+ * two drifts per turn and re-evaluates eta and the RF phase at every step
+ * (section 2.2, cProfile listing); the stationary form of that is
+ *   drift of weight w:  z     <- z - w C (eta0 + eta1 delta + eta2 delta^2) delta
+ *   kick  of weight w:  delta <- delta + w [A1 sin(k1 z + phi1) + A2 sin(k2 z + phi2)]
+ * with A_i = q V_i / (beta p0 c), k_i = 2 pi h_i / C and eta0 as above. It is
+ * the flow of H = -C (eta0 d^2/2 + eta1 d^3/3 + eta2 d^4/4)
+ *               + sum_i (A_i / k_i) cos(k_i z + phi_i).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double C, eta0, eta1, eta2;
+    double A1, k1, phi1;
+    double A2, k2, phi2;
+} or_rf2;
+
+static void drift2(const or_rf2 *c, double w, double *z, double dp)
+{
+    double eta = c->eta0 + c->eta1 * dp + c->eta2 * dp * dp;
+    *z = *z - (w * c->C) * eta * dp;
+}
+
+static double force2(const or_rf2 *c, double z)
+{
+    return c->A1 * sin(c->k1 * z + c->phi1) + c->A2 * sin(c->k2 * z + c->phi2);
+}
+
+static void kick2(const or_rf2 *c, double w, double z, double *dp)
+{
+    *dp = *dp + w * force2(c, z);
+}
+
+static double slip2(const or_rf2 *c, double dp)
+{
+    return -c->C * (c->eta0 + c->eta1 * dp + c->eta2 * dp * dp) * dp;
+}
+
+static void step2(const or_rf2 *c, int integrator, double w, double *z, double *dp)
+{
+    switch (integrator) {
+    case OR_EULER_CROMER:
+        drift2(c, w, z, *dp);
+        kick2(c, w, *z, dp);
+        break;
+    case OR_LEAPFROG:
+        drift2(c, 0.5 * w, z, *dp);
+        kick2(c, w, *z, dp);
+        drift2(c, 0.5 * w, z, *dp);
+        break;
+    case OR_RUTH4: {
+        double th = ruth_theta();
+        drift2(c, 0.5 * th * w, z, *dp);
+        kick2(c, th * w, *z, dp);
+        drift2(c, 0.5 * (1.0 - th) * w, z, *dp);
+        kick2(c, (1.0 - 2.0 * th) * w, *z, dp);
+        drift2(c, 0.5 * (1.0 - th) * w, z, *dp);
+        kick2(c, th * w, *z, dp);
+        drift2(c, 0.5 * th * w, z, *dp);
+        break;
+    }
+    case OR_RK4: {
+        double z0 = *z, d0 = *dp;
+        double k1z = slip2(c, d0), k1d = force2(c, z0);
+        double k2z = slip2(c, d0 + 0.5 * w * k1d), k2d = force2(c, z0 + 0.5 * w * k1z);
+        double k3z = slip2(c, d0 + 0.5 * w * k2d), k3d = force2(c, z0 + 0.5 * w * k2z);
+        double k4z = slip2(c, d0 + w * k3d), k4d = force2(c, z0 + w * k3z);
+        *z = z0 + (w / 6.0) * (k1z + 2.0 * k2z + 2.0 * k3z + k4z);
+        *dp = d0 + (w / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+        break;
+    }
+    }
+}
+
+/* As oracle_track for the extended map. h2 and V2 describe the second
+ * harmonic (V2 = 0: none); phi1, phi2 in radians. */
+int oracle_track_rf2(double *z, double *dp, int64_t n, int64_t turns, double C, double h,
+                     double V, double p0c, double m, double gamma_t, double q, double phi1,
+                     double h2, double V2, double phi2, double eta1, double eta2,
+                     int integrator, int substeps, double *moments, int threads)
+{
+    or_consts b;
+    if (n < 0 || turns < 0 || substeps < 1 || integrator < 0 || integrator > 3)
+        return -1;
+    if (or_make_consts(C, h, V, p0c, m, gamma_t, q, &b) != 0)
+        return -1;
+    if (!isfinite(phi1) || !isfinite(h2) || !isfinite(V2) || !isfinite(phi2) ||
+        !isfinite(eta1) || !isfinite(eta2) || (V2 != 0.0 && !(h2 > 0.0)))
+        return -1;
+    or_rf2 c;
+    c.C = C;
+    c.eta0 = b.eta;
+    c.eta1 = eta1;
+    c.eta2 = eta2;
+    c.A1 = b.A;
+    c.k1 = b.k;
+    c.phi1 = phi1;
+    c.A2 = q * V2 / (b.beta * p0c);
+    c.k2 = 2.0 * M_PI * h2 / C;
+    c.phi2 = phi2;
+#ifdef _OPENMP
+    int saved = omp_get_max_threads();
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    double w = 1.0 / (double)substeps;
+    for (int64_t t = 0; t < turns; ++t) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int s = 0; s < substeps; ++s)
+                step2(&c, integrator, w, &z[i], &dp[i]);
+        }
+        if (moments)
+            oracle_moments(z, dp, n, moments + 5 * t);
+    }
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use right now. */
 int oracle_max_threads(void)
 {
