@@ -67,6 +67,9 @@ def _load():
             lib.oracle_track_rf2.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + [d] * 13 + \
                 [ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
             lib.oracle_track_rf2.restype = ctypes.c_int
+            lib.oracle_track_program.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + \
+                [d] * 9 + [p] * 5 + [ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
+            lib.oracle_track_program.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -180,6 +183,42 @@ def hamiltonian_rf2(z, dp, rf2) -> np.ndarray:
     if A2 != 0.0:
         h = h + (A2 / k2) * np.cos(k2 * z + float(get("phi2_rad")))
     return h
+
+
+PROGRAM_FIELDS = ("voltage_V", "phi1_rad", "voltage2_V", "phi2_rad", "p0c_eV")
+
+
+def track_program(z, dp, turns: int, rf2, program, integrator="leapfrog", substeps: int = 1,
+                  with_moments: bool = True, threads: int = 0):
+    """Track copies of (z, dp) through the extended map with per-turn settings.
+
+    `rf2` gives the fixed parameters (ring fields, harmonic2, eta1, eta2; its
+    p0c_eV is the momentum before the first turn; its voltages and phases are
+    not used). `program` maps each of PROGRAM_FIELDS to an array with one
+    entry per turn: the RF voltages and phases of turn t and the reference
+    momentum after turn t.
+    """
+    integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    z = np.array(z, dtype=np.float64, copy=True, order="C").ravel()
+    dp = np.array(dp, dtype=np.float64, copy=True, order="C").ravel()
+    if z.shape != dp.shape:
+        raise ValueError("z and dp differ in length")
+    cols = []
+    for k in PROGRAM_FIELDS:
+        a = np.ascontiguousarray(program[k], dtype=np.float64).ravel()
+        if a.size < turns:
+            raise ValueError("programme field %s has %d < %d entries" % (k, a.size, turns))
+        cols.append(a)
+    get = (lambda k: rf2[k]) if isinstance(rf2, dict) else (lambda k: getattr(rf2, k))
+    fixed = [float(get(k)) for k in ("circumference_m", "harmonic", "p0c_eV", "mass_eV",
+                                     "gamma_t", "charge_e", "harmonic2", "eta1", "eta2")]
+    mom = np.empty((max(turns, 0), 5)) if with_moments else None
+    rc = _load().oracle_track_program(_ptr(z), _ptr(dp), z.size, int(turns), *fixed,
+                                      *[_ptr(a) for a in cols], integ, int(substeps),
+                                      _ptr(mom) if mom is not None else None, int(threads))
+    if rc != 0:
+        raise ValueError("invalid arguments to oracle_track_program")
+    return z, dp, mom
 
 
 def max_threads() -> int:

@@ -406,6 +406,176 @@ int oracle_track_rf2(double *z, double *dp, int64_t n, int64_t turns, double C, 
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * RF programme: the extended map with per-turn RF voltages and phases and a
+ * per-turn reference momentum (the "parameter changes of the accelerator
+ * setting" of the paper's hollow-bunch run, section 2.2).
+ *
+ * Turn n runs from reference momentum p_a = p(n) to p_b = p(n+1) (p(0) is the
+ * ring's p0c, p(n+1) the programme's entry n) with the RF settings of entry
+ * n. The RF gives a particle the energy q sum_i V_i sin(k_i z + phi_i), i.e.
+ * the momentum (energy gain) / beta_a with beta_a the reference beta at p_a;
+ * the reference itself gains p_b - p_a over the turn. Each kick of weight w
+ * (the scheme's kick weights sum to one) carries the fraction w of both, so
+ * the reference moves p_cur -> p_new = p_cur + w (p_b - p_a) and
+ *   absolute momentum:  P' = P + w q sum_i V_i sin(k_i z + phi_i) / beta_a,
+ *   with P = p_cur (1 + delta) and delta' = P' / p_new - 1, i.e.
+ *   delta' = (p_cur / p_new) delta + (p_cur - p_new) / p_new
+ *            + w q sum_i V_i sin(k_i z + phi_i) / (beta_a p_new)
+ * (the same expression rearranged so that delta never passes through 1 +
+ * delta, which would cost ~1e-13 of its relative precision per kick). A
+ * drift uses eta0 at the reference momentum current at that point of the
+ * turn. With p constant this is the extended map above with the entry's
+ * voltages and phases; a particle at z = 0, delta = 0 stays there when
+ * q V1 sin(phi1) / beta_a = p_b - p_a (the synchronous phase).
+ * RK4 integrates a vector field at fixed parameters and supports only
+ * programmes with a constant reference momentum.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double C, m, gamma_t, q, eta1, eta2, k1, k2;
+    /* this turn */
+    double V1, phi1, V2, phi2, beta_a, p_a, p_b;
+} or_prog;
+
+static double eta0_at(const or_prog *c, double p)
+{
+    double E = sqrt(p * p + c->m * c->m);
+    double gamma = E / c->m;
+    return 1.0 / (c->gamma_t * c->gamma_t) - 1.0 / (gamma * gamma);
+}
+
+static void drift_p(const or_prog *c, double w, double p_ref, double *z, double dp)
+{
+    double eta = eta0_at(c, p_ref) + c->eta1 * dp + c->eta2 * dp * dp;
+    *z = *z - (w * c->C) * eta * dp;
+}
+
+/* q sum_i V_i sin(k_i z + phi_i): energy gain in eV */
+static double energy_gain(const or_prog *c, double z)
+{
+    return c->q * (c->V1 * sin(c->k1 * z + c->phi1) + c->V2 * sin(c->k2 * z + c->phi2));
+}
+
+static void kick_p(const or_prog *c, double w, double p_cur, double p_new, double z, double *dp)
+{
+    *dp = (p_cur / p_new) * *dp + (p_cur - p_new) / p_new +
+          w * energy_gain(c, z) / (c->beta_a * p_new);
+}
+
+/* One step of length w turns, during which the reference goes from p0 to p1. */
+static void step_p(const or_prog *c, int integrator, double w, double p0, double p1, double *z,
+                   double *dp)
+{
+    double dpr = p1 - p0;
+    switch (integrator) {
+    case OR_EULER_CROMER:
+        drift_p(c, w, p0, z, *dp);
+        kick_p(c, w, p0, p1, *z, dp);
+        break;
+    case OR_LEAPFROG:
+        drift_p(c, 0.5 * w, p0, z, *dp);
+        kick_p(c, w, p0, p1, *z, dp);
+        drift_p(c, 0.5 * w, p1, z, *dp);
+        break;
+    case OR_RUTH4: {
+        double th = ruth_theta();
+        double q1 = p0 + th * dpr, q2 = p0 + (1.0 - th) * dpr;
+        drift_p(c, 0.5 * th * w, p0, z, *dp);
+        kick_p(c, th * w, p0, q1, *z, dp);
+        drift_p(c, 0.5 * (1.0 - th) * w, q1, z, *dp);
+        kick_p(c, (1.0 - 2.0 * th) * w, q1, q2, *z, dp);
+        drift_p(c, 0.5 * (1.0 - th) * w, q2, z, *dp);
+        kick_p(c, th * w, q2, p1, *z, dp);
+        drift_p(c, 0.5 * th * w, p1, z, *dp);
+        break;
+    }
+    case OR_RK4: { /* constant reference momentum only (checked by the caller) */
+        or_rf2 f;
+        f.C = c->C;
+        f.eta0 = eta0_at(c, p0);
+        f.eta1 = c->eta1;
+        f.eta2 = c->eta2;
+        f.A1 = c->q * c->V1 / (c->beta_a * p0);
+        f.k1 = c->k1;
+        f.phi1 = c->phi1;
+        f.A2 = c->q * c->V2 / (c->beta_a * p0);
+        f.k2 = c->k2;
+        f.phi2 = c->phi2;
+        step2(&f, OR_RK4, w, z, dp);
+        break;
+    }
+    }
+}
+
+/* As oracle_track_rf2 with per-turn settings: entry t of V1, phi1, V2, phi2
+ * applies to turn t, and p0c_after[t] is the reference momentum (eV) after
+ * turn t; p0c is the momentum before the first turn. Substeps split a turn
+ * into equal steps and its momentum step into equal parts. Returns -1 for
+ * invalid arguments, RK4 with a changing momentum included. */
+int oracle_track_program(double *z, double *dp, int64_t n, int64_t turns, double C, double h,
+                         double p0c, double m, double gamma_t, double q, double h2,
+                         double eta1, double eta2, const double *V1, const double *phi1,
+                         const double *V2, const double *phi2, const double *p0c_after,
+                         int integrator, int substeps, double *moments, int threads)
+{
+    or_consts b;
+    if (n < 0 || turns < 0 || substeps < 1 || integrator < 0 || integrator > 3)
+        return -1;
+    if (or_make_consts(C, h, 0.0, p0c, m, gamma_t, q, &b) != 0)
+        return -1;
+    if (!isfinite(h2) || !isfinite(eta1) || !isfinite(eta2))
+        return -1;
+    for (int64_t t = 0; t < turns; ++t) {
+        if (!isfinite(V1[t]) || !isfinite(phi1[t]) || !isfinite(V2[t]) || !isfinite(phi2[t]) ||
+            !(p0c_after[t] > 0.0) || !isfinite(p0c_after[t]) || (V2[t] != 0.0 && !(h2 > 0.0)))
+            return -1;
+        double before = t == 0 ? p0c : p0c_after[t - 1];
+        if (integrator == OR_RK4 && p0c_after[t] != before)
+            return -1;
+    }
+    or_prog c;
+    c.C = C;
+    c.m = m;
+    c.gamma_t = gamma_t;
+    c.q = q;
+    c.eta1 = eta1;
+    c.eta2 = eta2;
+    c.k1 = b.k;
+    c.k2 = 2.0 * M_PI * h2 / C;
+#ifdef _OPENMP
+    int saved = omp_get_max_threads();
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    double w = 1.0 / (double)substeps;
+    for (int64_t t = 0; t < turns; ++t) {
+        c.V1 = V1[t];
+        c.phi1 = phi1[t];
+        c.V2 = V2[t];
+        c.phi2 = phi2[t];
+        c.p_a = t == 0 ? p0c : p0c_after[t - 1];
+        c.p_b = p0c_after[t];
+        c.beta_a = c.p_a / sqrt(c.p_a * c.p_a + m * m);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int s = 0; s < substeps; ++s) {
+                double pa = c.p_a + (c.p_b - c.p_a) * ((double)s / substeps);
+                double pb = s + 1 == substeps ? c.p_b
+                                              : c.p_a + (c.p_b - c.p_a) * ((double)(s + 1) / substeps);
+                step_p(&c, integrator, w, pa, pb, &z[i], &dp[i]);
+            }
+        }
+        if (moments)
+            oracle_moments(z, dp, n, moments + 5 * t);
+    }
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use right now. */
 int oracle_max_threads(void)
 {
