@@ -70,6 +70,9 @@ def _load():
             lib.oracle_track_program.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + \
                 [d] * 9 + [p] * 5 + [ctypes.c_int, ctypes.c_int, p, ctypes.c_int]
             lib.oracle_track_program.restype = ctypes.c_int
+            lib.oracle_track_6d.argtypes = [p] * 6 + [ctypes.c_int64, ctypes.c_int64] + \
+                [d] * 13 + [p, ctypes.c_int, p, ctypes.c_int]
+            lib.oracle_track_6d.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -219,6 +222,39 @@ def track_program(z, dp, turns: int, rf2, program, integrator="leapfrog", subste
     if rc != 0:
         raise ValueError("invalid arguments to oracle_track_program")
     return z, dp, mom
+
+
+TWISS_FIELDS = ("Qx", "Qpx", "alpha_x", "beta_x", "Qy", "Qpy", "alpha_y", "beta_y")
+
+
+def track_6d(state, turns: int, rf2, twiss, integrator="leapfrog", with_moments: bool = True,
+             threads: int = 0):
+    """Track copies of a 6-D state through the transverse linear one-turn map
+    with chromatic phase advance, then the extended longitudinal map, per
+    turn. `state` maps z, dp, x, xp, y, yp to arrays; `twiss` maps
+    TWISS_FIELDS to numbers (tunes, chromaticities Q' per unit dp, alpha,
+    beta in metres). Returns (state dict, moments [turns, 15] or None): the
+    five moments of (z, dp), (x, xp) and (y, yp) after each turn."""
+    integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    keys = ("z", "dp", "x", "xp", "y", "yp")
+    arrs = [np.array(state[k], dtype=np.float64, copy=True, order="C").ravel() for k in keys]
+    if len({a.size for a in arrs}) != 1:
+        raise ValueError("state arrays differ in length")
+    tw = np.array([float(twiss[k]) for k in TWISS_FIELDS])
+    mom = np.empty((max(turns, 0), 15)) if with_moments else None
+    rc = _load().oracle_track_6d(*[_ptr(a) for a in arrs], arrs[0].size, int(turns),
+                                 *_ring_values(rf2), *_rf2_values(rf2), _ptr(tw), integ,
+                                 _ptr(mom) if mom is not None else None, int(threads))
+    if rc != 0:
+        raise ValueError("invalid arguments to oracle_track_6d")
+    return dict(zip(keys, arrs)), mom
+
+
+def courant_snyder(u, up, alpha, beta) -> np.ndarray:
+    """Courant-Snyder invariant gamma u^2 + 2 alpha u u' + beta u'^2."""
+    u = np.asarray(u, dtype=np.float64)
+    up = np.asarray(up, dtype=np.float64)
+    return (1.0 + alpha * alpha) / beta * u * u + 2.0 * alpha * u * up + beta * up * up
 
 
 def max_threads() -> int:

@@ -576,6 +576,97 @@ int oracle_track_program(double *z, double *dp, int64_t n, int64_t turns, double
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Transverse linear one-turn map (paper, section 1.1.1: the same linear
+ * transfer matrix acts on every particle's transverse state each turn),
+ * with the chromatic phase advance that couples it to the longitudinal
+ * momentum. Per plane u in {x, y}, with the Twiss parameters alpha, beta
+ * (gamma = (1 + alpha^2) / beta) at the observation point, tune Q and
+ * chromaticity Q' (tune shift per unit delta):
+ *   phi = 2 pi (Q + Q' delta)
+ *   u   <- (cos phi + alpha sin phi) u + beta sin phi u'
+ *   u'  <- -gamma sin phi u + (cos phi - alpha sin phi) u'
+ * One turn applies the transverse map with the turn's starting delta, then
+ * the longitudinal step of the extended map.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double Q, Qp, alpha, beta, gamma;
+} or_plane;
+
+/* The rotation depends on the tune modulo one: the integer part is dropped
+ * exactly (Q - floor(Q) has no rounding error) before the phase is formed,
+ * so its rounding is that of a phase below 2 pi rather than of 2 pi Q. */
+static void transverse(const or_plane *p, double dp, double *u, double *up)
+{
+    double phi = 2.0 * M_PI * ((p->Q - floor(p->Q)) + p->Qp * dp);
+    double c = cos(phi), s = sin(phi);
+    double u0 = *u, v0 = *up;
+    *u = (c + p->alpha * s) * u0 + p->beta * s * v0;
+    *up = -p->gamma * s * u0 + (c - p->alpha * s) * v0;
+}
+
+/* As oracle_track_rf2 with a transverse state (x, xp, y, yp) besides (z, dp).
+ * `tw` = {Qx, Qpx, alpha_x, beta_x, Qy, Qpy, alpha_y, beta_y}. If `moments`
+ * is not NULL it receives turns rows of 15 values: the 5 moments of (z, dp),
+ * then of (x, xp), then of (y, yp), each as oracle_moments. */
+int oracle_track_6d(double *z, double *dp, double *x, double *xp, double *y, double *yp,
+                    int64_t n, int64_t turns, double C, double h, double V, double p0c,
+                    double m, double gamma_t, double q, double phi1, double h2, double V2,
+                    double phi2, double eta1, double eta2, const double tw[8], int integrator,
+                    double *moments, int threads)
+{
+    or_consts b;
+    if (n < 0 || turns < 0 || integrator < 0 || integrator > 3)
+        return -1;
+    if (or_make_consts(C, h, V, p0c, m, gamma_t, q, &b) != 0)
+        return -1;
+    if (!isfinite(phi1) || !isfinite(h2) || !isfinite(V2) || !isfinite(phi2) ||
+        !isfinite(eta1) || !isfinite(eta2) || (V2 != 0.0 && !(h2 > 0.0)))
+        return -1;
+    for (int i = 0; i < 8; ++i)
+        if (!isfinite(tw[i]))
+            return -1;
+    if (!(tw[3] > 0.0) || !(tw[7] > 0.0))
+        return -1;
+    or_rf2 c;
+    c.C = C;
+    c.eta0 = b.eta;
+    c.eta1 = eta1;
+    c.eta2 = eta2;
+    c.A1 = b.A;
+    c.k1 = b.k;
+    c.phi1 = phi1;
+    c.A2 = q * V2 / (b.beta * p0c);
+    c.k2 = 2.0 * M_PI * h2 / C;
+    c.phi2 = phi2;
+    or_plane px = {tw[0], tw[1], tw[2], tw[3], (1.0 + tw[2] * tw[2]) / tw[3]};
+    or_plane py = {tw[4], tw[5], tw[6], tw[7], (1.0 + tw[6] * tw[6]) / tw[7]};
+#ifdef _OPENMP
+    int saved = omp_get_max_threads();
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    for (int64_t t = 0; t < turns; ++t) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            transverse(&px, dp[i], &x[i], &xp[i]);
+            transverse(&py, dp[i], &y[i], &yp[i]);
+            step2(&c, integrator, 1.0, &z[i], &dp[i]);
+        }
+        if (moments) {
+            oracle_moments(z, dp, n, moments + 15 * t);
+            oracle_moments(x, xp, n, moments + 15 * t + 5);
+            oracle_moments(y, yp, n, moments + 15 * t + 10);
+        }
+    }
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use right now. */
 int oracle_max_threads(void)
 {
