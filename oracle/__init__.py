@@ -73,6 +73,9 @@ def _load():
             lib.oracle_track_6d.argtypes = [p] * 6 + [ctypes.c_int64, ctypes.c_int64] + \
                 [d] * 13 + [p, ctypes.c_int, p, ctypes.c_int]
             lib.oracle_track_6d.restype = ctypes.c_int
+            lib.oracle_track_wake.argtypes = [p, p, ctypes.c_int64, ctypes.c_int64] + [d] * 13 + \
+                [p, ctypes.c_int, p, ctypes.c_int]
+            lib.oracle_track_wake.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -255,6 +258,42 @@ def courant_snyder(u, up, alpha, beta) -> np.ndarray:
     u = np.asarray(u, dtype=np.float64)
     up = np.asarray(up, dtype=np.float64)
     return (1.0 + alpha * alpha) / beta * u * u + 2.0 * alpha * u * up + beta * up * up
+
+
+WAKE_FIELDS = ("model", "R_s", "f_r", "Q", "intensity", "n_slices", "z_lo", "z_hi")
+E_CHARGE = 1.602176634e-19
+C_LIGHT = 299792458.0
+
+
+def track_wake(z, dp, turns: int, rf2, wake, integrator="leapfrog", with_moments: bool = True,
+               threads: int = 0):
+    """Track copies of (z, dp) through the extended map with a longitudinal
+    wake kick after every turn. `wake` maps WAKE_FIELDS to numbers: model (0
+    resonator, 1 constant wake R_s V/C), R_s (ohm), f_r (Hz), Q, intensity
+    (particles in the bunch), n_slices, z_lo, z_hi (m)."""
+    integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    z = np.array(z, dtype=np.float64, copy=True, order="C").ravel()
+    dp = np.array(dp, dtype=np.float64, copy=True, order="C").ravel()
+    if z.shape != dp.shape:
+        raise ValueError("z and dp differ in length")
+    wk = np.array([float(wake.get(k, 0.0)) for k in WAKE_FIELDS])
+    mom = np.empty((max(turns, 0), 5)) if with_moments else None
+    rc = _load().oracle_track_wake(_ptr(z), _ptr(dp), z.size, int(turns), *_ring_values(rf2),
+                                   *_rf2_values(rf2), _ptr(wk), integ,
+                                   _ptr(mom) if mom is not None else None, int(threads))
+    if rc != 0:
+        raise ValueError("invalid arguments to oracle_track_wake")
+    return z, dp, mom
+
+
+def resonator_wake(tau, R_s, f_r, Q):
+    """Resonator wake function W(tau) in V/C (tau in s; W(0) is half the limit)."""
+    tau = np.asarray(tau, dtype=np.float64)
+    w_r = 2 * np.pi * f_r
+    a = w_r / (2 * Q)
+    wb = np.sqrt(w_r * w_r - a * a)
+    w = 2 * a * R_s * np.exp(-a * tau) * (np.cos(wb * tau) - a / wb * np.sin(wb * tau))
+    return np.where(tau == 0.0, a * R_s, np.where(tau > 0.0, w, 0.0))
 
 
 def max_threads() -> int:

@@ -29,6 +29,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -664,6 +665,179 @@ int oracle_track_6d(double *z, double *dp, double *x, double *xp, double *y, dou
 #ifdef _OPENMP
     omp_set_num_threads(saved);
 #endif
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Longitudinal wake kick (the impedance effects the paper's conclusion names
+ * as the memory-bound next step, section 3). Once per turn, after the map
+ * step: the bunch is cut into n_slices equal slices over [z_lo, z_hi)
+ * (particles outside are neither counted nor kicked); the wake potential at
+ * slice centre c_k is
+ *   V_k = Q_mp sum_{j >= k} count_j W((c_j - c_k) / (beta c)),
+ * the charge of every slice at or ahead of it (z grows toward the head)
+ * times the wake function, Q_mp = q e N_b / N_mp the charge of one
+ * macro-particle; a particle at z gets V(z) by linear interpolation between
+ * the centres (constant beyond the first and last centre) and
+ *   delta <- delta - q V(z) / (beta p0 c)      (V in volts, p0 c in eV).
+ * Wake function of a resonator (shunt impedance R_s, resonance frequency
+ * f_r = omega_r / 2 pi, quality factor Q > 1/2), alpha = omega_r / (2 Q),
+ * omega' = sqrt(omega_r^2 - alpha^2):
+ *   W(tau) = 2 alpha R_s exp(-alpha tau) (cos omega' tau - alpha/omega' sin omega' tau), tau > 0,
+ *   W(0)   = alpha R_s (half the limit: a charge sees half its own wake).
+ * model 1 is a constant wake W(tau > 0) = R_s, W(0) = R_s / 2 (the potential
+ * is then the charge ahead; used to pin the slicing).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int model;
+    double Rs, alpha, omega_bar;
+    double kappa;           /* q Q_mp / (beta p0 c): delta kick per volt of potential per count */
+    double z_lo, dz;        /* slice edges z_lo + k dz */
+    int64_t n_slices;
+    double tau_per_slice;   /* dz / (beta c) */
+} or_wake;
+
+static double wake_fn(const or_wake *w, double tau)
+{
+    if (w->model == 1)
+        return tau > 0.0 ? w->Rs : 0.5 * w->Rs;
+    if (tau == 0.0)
+        return w->alpha * w->Rs;
+    return 2.0 * w->alpha * w->Rs * exp(-w->alpha * tau) *
+           (cos(w->omega_bar * tau) - w->alpha / w->omega_bar * sin(w->omega_bar * tau));
+}
+
+/* Slice of z, or -1 outside [z_lo, z_lo + n_slices dz). */
+static int64_t slice_of(const or_wake *w, double z)
+{
+    double u = (z - w->z_lo) / w->dz;
+    if (!(u >= 0.0))
+        return -1;
+    double f = floor(u);
+    if (f >= (double)w->n_slices)
+        return -1;
+    return (int64_t)f;
+}
+
+/* Wm[m] = W(m dz / (beta c)): the wake at the lags between slice centres. */
+static void wake_kick(const or_wake *w, const double *Wm, const double *z, double *dp, int64_t n,
+                      int64_t *count, double *V)
+{
+    int64_t ns = w->n_slices;
+    for (int64_t k = 0; k < ns; ++k)
+        count[k] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = slice_of(w, z[i]);
+        if (k >= 0)
+            count[k] += 1;
+    }
+    for (int64_t k = 0; k < ns; ++k) {
+        double v = 0.0;
+        for (int64_t j = k; j < ns; ++j)
+            v += (double)count[j] * Wm[j - k];
+        V[k] = v;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (slice_of(w, z[i]) < 0)
+            continue;
+        double s = (z[i] - w->z_lo) / w->dz - 0.5; /* in slice-centre units */
+        double pot;
+        if (s <= 0.0) {
+            pot = V[0];
+        } else if (s >= (double)(ns - 1)) {
+            pot = V[ns - 1];
+        } else {
+            double k0 = floor(s);
+            double f = s - k0;
+            int64_t k = (int64_t)k0;
+            pot = (1.0 - f) * V[k] + f * V[k + 1];
+        }
+        dp[i] = dp[i] - w->kappa * pot;
+    }
+}
+
+/* As oracle_track_rf2 with a wake kick after every map step. wk = {model,
+ * R_s (ohm; model 1: V/C), f_r (Hz), Q, N_b (particles in the bunch),
+ * n_slices, z_lo, z_hi}. */
+int oracle_track_wake(double *z, double *dp, int64_t n, int64_t turns, double C, double h,
+                      double V, double p0c, double m, double gamma_t, double q, double phi1,
+                      double h2, double V2, double phi2, double eta1, double eta2,
+                      const double wk[8], int integrator, double *moments, int threads)
+{
+    or_consts b;
+    if (n < 0 || turns < 0 || integrator < 0 || integrator > 3)
+        return -1;
+    if (or_make_consts(C, h, V, p0c, m, gamma_t, q, &b) != 0)
+        return -1;
+    if (!isfinite(phi1) || !isfinite(h2) || !isfinite(V2) || !isfinite(phi2) ||
+        !isfinite(eta1) || !isfinite(eta2) || (V2 != 0.0 && !(h2 > 0.0)))
+        return -1;
+    for (int i = 0; i < 8; ++i)
+        if (!isfinite(wk[i]))
+            return -1;
+    int model = (int)wk[0];
+    int64_t ns = (int64_t)wk[5];
+    if ((model != 0 && model != 1) || (double)model != wk[0] || (double)ns != wk[5] || ns < 1 ||
+        ns > (1 << 20) || !(wk[7] > wk[6]) || !(wk[4] >= 0.0) ||
+        (model == 0 && (!(wk[2] > 0.0) || !(wk[3] > 0.5))))
+        return -1;
+    or_rf2 c;
+    c.C = C;
+    c.eta0 = b.eta;
+    c.eta1 = eta1;
+    c.eta2 = eta2;
+    c.A1 = b.A;
+    c.k1 = b.k;
+    c.phi1 = phi1;
+    c.A2 = q * V2 / (b.beta * p0c);
+    c.k2 = 2.0 * M_PI * h2 / C;
+    c.phi2 = phi2;
+    const double e_charge = 1.602176634e-19, c_light = 299792458.0;
+    or_wake w;
+    w.model = model;
+    w.Rs = wk[1];
+    double omega_r = 2.0 * M_PI * wk[2];
+    w.alpha = model == 0 ? omega_r / (2.0 * wk[3]) : 0.0;
+    w.omega_bar = model == 0 ? sqrt(omega_r * omega_r - w.alpha * w.alpha) : 0.0;
+    w.n_slices = ns;
+    w.z_lo = wk[6];
+    w.dz = (wk[7] - wk[6]) / (double)ns;
+    w.tau_per_slice = w.dz / (b.beta * c_light);
+    double q_mp = n > 0 ? q * e_charge * wk[4] / (double)n : 0.0;
+    w.kappa = q * q_mp / (b.beta * p0c);
+    int64_t *count = (int64_t *)malloc(sizeof(int64_t) * (size_t)ns);
+    double *Vk = (double *)malloc(sizeof(double) * (size_t)ns);
+    double *Wm = (double *)malloc(sizeof(double) * (size_t)ns);
+    if (!count || !Vk || !Wm) {
+        free(count);
+        free(Vk);
+        free(Wm);
+        return -1;
+    }
+    for (int64_t k = 0; k < ns; ++k)
+        Wm[k] = wake_fn(&w, (double)k * w.tau_per_slice);
+#ifdef _OPENMP
+    int saved = omp_get_max_threads();
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    for (int64_t t = 0; t < turns; ++t) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            step2(&c, integrator, 1.0, &z[i], &dp[i]);
+        wake_kick(&w, Wm, z, dp, n, count, Vk);
+        if (moments)
+            oracle_moments(z, dp, n, moments + 5 * t);
+    }
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    free(count);
+    free(Vk);
+    free(Wm);
     return 0;
 }
 
