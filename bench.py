@@ -10,7 +10,10 @@ on stdout; progress goes to stderr.
 
 Other workloads (--workload): unfused (one launch per turn, HBM roofline
 sweep), precision (FP32+Kahan vs FP64, 1e7 particles), batched (256 uneven
-bunches), serving (Poisson request stream through the engine), ksweep.
+bunches), serving (Poisson request stream through the engine), ksweep,
+schemes (every integrator), rf2 (double-harmonic RF, slip factor to second
+order in dp), program (per-turn RF settings and a momentum ramp), 6d
+(transverse linear map with chromaticity plus the longitudinal step).
 """
 from __future__ import annotations
 
@@ -51,6 +54,26 @@ FLOPS_PER_PT = {
     "ruth4": 8 + 6 + 3 * SIN_FLOPS + 8,
     "rk4": 32 + 4 * SIN_FLOPS + 8,
 }
+# Extended map (two RF harmonics with phase offsets, slip factor quadratic in
+# dp): drift = 2 FMA for eta(dp) + 1 FMA = 6; kick per harmonic = the sine
+# above + phase offset add + the FMA into dp = SIN_FLOPS + 3.
+RF2_DRIFT, RF2_KICK = 6, 2 * (SIN_FLOPS + 3)
+RF2_FLOPS_PER_PT = {
+    "euler_cromer": RF2_DRIFT + RF2_KICK + 8,
+    "leapfrog": 2 * RF2_DRIFT + RF2_KICK + 8,
+    "ruth4": 4 * RF2_DRIFT + 3 * RF2_KICK + 8,
+    "rk4": 4 * RF2_DRIFT + 4 * RF2_KICK + 26 + 8,
+}
+# RF programme: one more FMA per kick (the reference step (p/p') delta + (p - p')/p').
+RF2_REF_STEP = {"euler_cromer": 2, "leapfrog": 2, "ruth4": 6, "rk4": 0}
+# 6-D map, per transverse plane: phase FMA 2, reduction subtract 1, r^2 1,
+# t = 1/2 - |r| 1, t^2 1, two sine polynomials (7 FMA + final multiply each)
+# 30, Twiss matrix (2 FMA for the diagonal, 2 multiplies, 2 x (multiply + FMA))
+# 12 = 48; the longitudinal step without its moments, plus 5 sums (8 flops)
+# for each of the three planes.
+POLY_FLOPS = 2 * (_sin_terms() - 1) + 1
+PLANE_FLOPS = 2 + 1 + 1 + 1 + 1 + 2 * POLY_FLOPS + 12
+SIXD_FLOPS_PER_PT = {k: 2 * PLANE_FLOPS + (v - 8) + 3 * 8 for k, v in RF2_FLOPS_PER_PT.items()}
 STATE_BYTES_PER_PARTICLE = 16  # z, dp FP64 (or FP32 hi + comp for both)
 
 
@@ -61,7 +84,7 @@ def log(*a):
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1610_05801_amd", "csrc")
-    for f in ("kernels.hip", "ltrk_device.h", "sinpi_coeffs.h"):
+    for f in ("kernels.hip", "wave.h", "ltrk_device.h", "sinpi_coeffs.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -425,6 +448,178 @@ def bench_schemes(args):
           flush=True)
 
 
+def bench_rf2(args):
+    """Extended map (double-harmonic RF, phase offsets, slip factor quadratic
+    in dp), FP64, every scheme at 1e6 particles x 1e4 turns with moments
+    every turn; leap-frog also through the single-harmonic kernel for the
+    cost of the second harmonic. Kernel time from HIP events."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_DOUBLE_RF, SPS_RING, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n, T = args.particles, args.turns
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+    rows = []
+    cases = [(i, "rf2") for i in ("euler_cromer", "leapfrog", "ruth4", "rk4")]
+    cases.append(("leapfrog", "single"))
+    for integ, kind in cases:
+        z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+        if kind == "rf2":
+            call = lambda: ltrk.ltrk_track_rf2_f64(z, dp, T, SPS_DOUBLE_RF, integ, mom,
+                                                   stream=stream)
+            flops = RF2_FLOPS_PER_PT[integ]
+        else:
+            call = lambda: ltrk.ltrk_track_f64(z, dp, T, SPS_RING, integ, mom, stream=stream)
+            flops = FLOPS_PER_PT[integ]
+        with torch.cuda.stream(stream):
+            call()
+            stream.synchronize()
+            ltrk.ltrk_timing_enable(True)
+            ltrk.ltrk_timing_take()
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            tm = ltrk.ltrk_timing_take()
+            ltrk.ltrk_timing_enable(False)
+        launches = max(tm["track_launches"], 1)
+        kern = tm["track_ms"] / launches
+        per_launch = n * T / launches
+        row = {"map": kind, "integrator": integ, "particle_turns_per_s": n * T / dt,
+               "kernel_particle_turns_per_s": per_launch / (kern * 1e-3),
+               "flops_per_particle_turn": flops,
+               "kernel_tflops": flops * per_launch / (kern * 1e-3) / 1e12,
+               "frac_fp64_peak": flops * per_launch / (kern * 1e-3) / 1e12
+               / FP64_VECTOR_PEAK_TFLOPS,
+               "avg_launch_ms": kern, "finalize_ms": tm["finalize_ms"]}
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"workload": "extended map: %d particles x %d turns, double RF "
+                      "(h2 = 2h, V2 = V/4, counter-phase), eta(dp) to second order"
+                      % (n, T), "rows": rows}), flush=True)
+
+
+def _ramp_programme(turns, p0, v1, m, rel_per_turn=2e-6):
+    """Synchronous-phase momentum ramp with a modulated RF voltage and a
+    second harmonic in counter-phase: every record changes every turn."""
+    n = np.arange(turns)
+    p_after = p0 * (1 + rel_per_turn * (n + 1))
+    p_before = np.concatenate([[p0], p_after[:-1]])
+    volts = v1 * (1 + 0.2 * np.sin(n / 300.0))
+    beta = p_before / np.sqrt(p_before ** 2 + m * m)
+    phi = np.arcsin(beta * (p_after - p_before) / volts)
+    return dict(voltage_V=volts, phi1_rad=phi, voltage2_V=0.25 * volts,
+                phi2_rad=np.full(turns, math.pi), p0c_eV=p_after)
+
+
+def bench_program(args):
+    """RF programme: 1e6 particles x 1e4 turns through a 2% momentum ramp
+    (records change every turn), FP64, moments every turn, every scheme that
+    supports a ramp, plus RK4 and leap-frog on a constant-momentum programme.
+    Kernel time from HIP events; wall time includes building and uploading
+    the per-turn records."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_DOUBLE_RF, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n, T = args.particles, args.turns
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+    ramp = _ramp_programme(T, SPS_DOUBLE_RF["p0c_eV"], SPS_DOUBLE_RF["voltage_V"],
+                           SPS_DOUBLE_RF["mass_eV"])
+    flat = dict(ramp, p0c_eV=np.full(T, SPS_DOUBLE_RF["p0c_eV"]),
+                phi1_rad=np.zeros(T))
+    rows = []
+    cases = [(i, "ramp", ramp) for i in ("euler_cromer", "leapfrog", "ruth4")]
+    cases += [("leapfrog", "flat", flat), ("rk4", "flat", flat)]
+    for integ, kind, prog in cases:
+        z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+        recs = ltrk.RfTurn.array(prog, T)
+        call = lambda: ltrk.ltrk_track_program_f64(z, dp, T, SPS_DOUBLE_RF, recs, integ, mom,
+                                                   stream=stream)
+        flops = RF2_FLOPS_PER_PT[integ] + (RF2_REF_STEP[integ] if kind == "ramp" else 0)
+        with torch.cuda.stream(stream):
+            call()
+            stream.synchronize()
+            ltrk.ltrk_timing_enable(True)
+            ltrk.ltrk_timing_take()
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            tm = ltrk.ltrk_timing_take()
+            ltrk.ltrk_timing_enable(False)
+        launches = max(tm["track_launches"], 1)
+        kern = tm["track_ms"] / launches
+        per_launch = n * T / launches
+        row = {"programme": kind, "integrator": integ, "particle_turns_per_s": n * T / dt,
+               "kernel_particle_turns_per_s": per_launch / (kern * 1e-3),
+               "flops_per_particle_turn": flops,
+               "kernel_tflops": flops * per_launch / (kern * 1e-3) / 1e12,
+               "frac_fp64_peak": flops * per_launch / (kern * 1e-3) / 1e12
+               / FP64_VECTOR_PEAK_TFLOPS,
+               "avg_launch_ms": kern, "finalize_ms": tm["finalize_ms"]}
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"workload": "RF programme: %d particles x %d turns, 2%% momentum ramp "
+                      "at the synchronous phase, V modulated, double RF" % (n, T),
+                      "rows": rows}), flush=True)
+
+def bench_6d(args):
+    """6-D map: 1e6 particles x 1e4 turns (leap-frog and Ruth4), transverse
+    Twiss rotation with chromaticity then the double-RF longitudinal step,
+    moments of the three planes every turn. Kernel time from HIP events."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_DOUBLE_RF, SPS_TWISS, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    n, T = args.particles, args.turns
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    rng = np.random.default_rng(SEEDS["paper_scale"] + 1)
+    ex = 2e-8  # geometric emittance (m rad) of the transverse Gaussian
+    x0 = np.sqrt(ex * SPS_TWISS["beta_x"]) * rng.standard_normal(n)
+    xp0 = np.sqrt(ex / SPS_TWISS["beta_x"]) * rng.standard_normal(n)
+    y0 = np.sqrt(ex * SPS_TWISS["beta_y"]) * rng.standard_normal(n)
+    yp0 = np.sqrt(ex / SPS_TWISS["beta_y"]) * rng.standard_normal(n)
+    mom = torch.empty((T, 3, 5), dtype=torch.float64, device=dev)
+    rows = []
+    for integ in ("leapfrog", "ruth4"):
+        arrs = [torch.as_tensor(a).to(dev) for a in (z0, dp0, x0, xp0, y0, yp0)]
+        call = lambda: ltrk.ltrk_track_6d_f64(*arrs, T, SPS_DOUBLE_RF, SPS_TWISS, integ, mom,
+                                              stream=stream)
+        flops = SIXD_FLOPS_PER_PT[integ]
+        with torch.cuda.stream(stream):
+            call()
+            stream.synchronize()
+            ltrk.ltrk_timing_enable(True)
+            ltrk.ltrk_timing_take()
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            tm = ltrk.ltrk_timing_take()
+            ltrk.ltrk_timing_enable(False)
+        launches = max(tm["track_launches"], 1)
+        kern = tm["track_ms"] / launches
+        per_launch = n * T / launches
+        row = {"map": "6d", "integrator": integ, "particle_turns_per_s": n * T / dt,
+               "kernel_particle_turns_per_s": per_launch / (kern * 1e-3),
+               "flops_per_particle_turn": flops,
+               "kernel_tflops": flops * per_launch / (kern * 1e-3) / 1e12,
+               "frac_fp64_peak": flops * per_launch / (kern * 1e-3) / 1e12
+               / FP64_VECTOR_PEAK_TFLOPS,
+               "avg_launch_ms": kern, "finalize_ms": tm["finalize_ms"]}
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"workload": "6-D map: %d particles x %d turns, double RF, chromatic "
+                      "transverse rotation, moments of 3 planes every turn" % (n, T),
+                      "rows": rows}), flush=True)
+
+
 def _matched_sigma_z(ltrk, ring, sigma_dp):
     d = ltrk.ltrk_derive(ring)
     return sigma_dp * d["slip_length"] / d["omega_s"]
@@ -630,7 +825,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
-                             "counters", "schemes"])
+                             "counters", "schemes", "rf2", "program", "6d"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
@@ -656,7 +851,8 @@ def main():
         return
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
-     "counters": bench_counters, "schemes": bench_schemes}[args.workload](args)
+     "counters": bench_counters, "schemes": bench_schemes,
+     "rf2": bench_rf2, "program": bench_program, "6d": bench_6d}[args.workload](args)
 
 
 if __name__ == "__main__":

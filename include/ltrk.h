@@ -131,6 +131,94 @@ int ltrk_track_f32c(float* z, float* dp, float* z_comp, float* dp_comp, int64_t 
                     int64_t turns, const ltrk_ring* ring, int integrator,
                     ltrk_moments* moments, void* stream);
 
+/* Extended RF and slippage: a second RF harmonic, RF phase offsets and a slip
+ * factor expanded in delta. The paper's hollow-bunch study (section 2.2,
+ * profile) applies two RF kicks and re-evaluates eta and the RF phase every
+ * step; this is the stationary form of that map:
+ *   drift:  z     <- z - w * C * (eta0 + eta1 delta + eta2 delta^2) * delta
+ *   kick:   delta <- delta + w * sum_i (q V_i / (beta p0 c)) sin(2 pi h_i z / C + phi_i)
+ * with eta0 = 1/gamma_t^2 - 1/gamma^2 from `ring`, i = 1 from `ring`
+ * (harmonic, voltage_V) and i = 2 from the fields below (voltage2_V = 0: no
+ * second harmonic). phi_i in radians; harmonic2 integer valued and > 0 when
+ * voltage2_V != 0; eta1, eta2 dimensionless and finite. */
+typedef struct ltrk_rf2 {
+    ltrk_ring ring;
+    double phi1_rad;
+    double harmonic2;
+    double voltage2_V;
+    double phi2_rad;
+    double eta1;
+    double eta2;
+} ltrk_rf2;
+
+/* As ltrk_track_f64 (FP64 state, same arrays, moments and stream rules) for
+ * the extended map. EINVAL for an invalid ring or extension field. */
+int ltrk_track_rf2_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                       int integrator, ltrk_moments* moments, void* stream);
+
+/* One turn of an RF programme: the RF settings of that turn and the reference
+ * momentum after it. The paper's hollow-bunch run changes the machine
+ * settings while it tracks (section 2.2); this is the per-turn form. */
+typedef struct ltrk_rf_turn {
+    double voltage_V;   /* V1 during the turn */
+    double phi1_rad;    /* phase of harmonic 1 */
+    double voltage2_V;  /* V2 during the turn (0: no second harmonic) */
+    double phi2_rad;    /* phase of harmonic 2 */
+    double p0c_eV;      /* reference momentum after the turn, > 0 */
+} ltrk_rf_turn;
+
+/* The extended map with per-turn settings (FP64 state; arrays, moments and
+ * stream rules as ltrk_track_f64). `rf` gives what stays fixed: the ring
+ * (its p0c_eV is the reference momentum before the first turn; its voltage_V
+ * and rf's phi1_rad, voltage2_V, phi2_rad are not used), harmonic2, eta1,
+ * eta2. `program`: host array of `turns` entries, entry t for turn t, read
+ * before the call returns.
+ * Turn t runs the reference from p_a (the previous entry's p0c_eV, or the
+ * ring's) to p_b (entry t's). The RF gives a particle the energy
+ * E_t(z) = q sum_i V_i sin(2 pi h_i z / C + phi_i), a momentum E_t(z) / beta_a
+ * with beta_a the reference beta at p_a. A kick of weight w (the scheme's
+ * kick weights sum to one) carries the share w of that gain and of the
+ * reference step: with the reference moving p -> p' = p + w (p_b - p_a),
+ *   delta <- (p / p') delta + (p - p') / p' + w E_t(z) / (beta_a p').
+ * A drift uses eta0 at the reference momentum current at that point of the
+ * turn. With a constant momentum and constant settings this is
+ * ltrk_track_rf2_f64. EINVAL for an invalid ring, extension field or
+ * programme entry (non-finite, p0c_eV <= 0, voltage2_V != 0 without a valid
+ * harmonic2); EUNSUPPORTED for RK4 with a changing momentum and for a stream
+ * that is being captured into a graph (the programme is uploaded by a copy
+ * that a graph would replay from reused host memory). */
+int ltrk_track_program_f64(double* z, double* dp, int64_t n, int64_t turns,
+                           const ltrk_rf2* rf, const ltrk_rf_turn* program, int integrator,
+                           ltrk_moments* moments, void* stream);
+
+/* Twiss parameters and tunes of the two transverse planes at the
+ * observation point (section 1.1.1: one linear transfer matrix per turn). */
+typedef struct ltrk_twiss {
+    double q_x;      /* tune (its integer part does not matter) */
+    double qp_x;     /* chromaticity: tune shift per unit delta */
+    double alpha_x;
+    double beta_x;   /* metres, > 0 */
+    double q_y;
+    double qp_y;
+    double alpha_y;
+    double beta_y;
+} ltrk_twiss;
+
+/* Track n particles with a 6-D FP64 state (device arrays of n doubles each,
+ * updated in place; x, y in metres, xp, yp in radians) for `turns` turns.
+ * One turn: per plane u the Twiss rotation by phi = 2 pi (Q + Q' delta) with
+ * the turn's starting delta,
+ *   u  <- (cos phi + alpha sin phi) u + beta sin phi u'
+ *   u' <- -gamma sin phi u + (cos phi - alpha sin phi) u',  gamma = (1 + alpha^2) / beta,
+ * then one step of the extended longitudinal map (as ltrk_track_rf2_f64).
+ * moments: device array of 3 * turns rows or NULL; rows 3t, 3t + 1, 3t + 2
+ * hold the moments of (z, dp), (x, xp), (y, yp) after turn t + 1 (means,
+ * rms and rms emittance of each pair). EINVAL for an invalid ring, extension
+ * or Twiss field (non-finite, beta <= 0). */
+int ltrk_track_6d_f64(double* z, double* dp, double* x, double* xp, double* y, double* yp,
+                      int64_t n, int64_t turns, const ltrk_rf2* rf, const ltrk_twiss* twiss,
+                      int integrator, ltrk_moments* moments, void* stream);
+
 /* Moments of the current state (one row) into the device row `out`. */
 int ltrk_moments_f64(const double* z, const double* dp, int64_t n, ltrk_moments* out,
                      void* stream);

@@ -69,6 +69,58 @@ class Ring(ctypes.Structure):
         return cls(**{k: float(getattr(r, k)) for k, _ in cls._fields_})
 
 
+class Rf2(ctypes.Structure):
+    _fields_ = [("ring", Ring), ("phi1_rad", c_d), ("harmonic2", c_d), ("voltage2_V", c_d),
+                ("phi2_rad", c_d), ("eta1", c_d), ("eta2", c_d)]
+
+    @classmethod
+    def of(cls, r) -> "Rf2":
+        if isinstance(r, Rf2):
+            return r
+        get = (lambda k: r[k]) if isinstance(r, dict) else (lambda k: getattr(r, k))
+        return cls(Ring.of(r), *[float(get(k)) for k in ("phi1_rad", "harmonic2", "voltage2_V",
+                                                        "phi2_rad", "eta1", "eta2")])
+
+
+class RfTurn(ctypes.Structure):
+    _fields_ = [("voltage_V", c_d), ("phi1_rad", c_d), ("voltage2_V", c_d), ("phi2_rad", c_d),
+                ("p0c_eV", c_d)]
+
+    FIELDS = ("voltage_V", "phi1_rad", "voltage2_V", "phi2_rad", "p0c_eV")
+
+    @classmethod
+    def array(cls, program, turns: int):
+        """A ctypes array of `turns` entries from a dict of per-turn arrays
+        (keys FIELDS) or a sequence of RfTurn."""
+        if isinstance(program, ctypes.Array) and len(program) >= turns:
+            return program
+        arr = (cls * max(int(turns), 1))()
+        if isinstance(program, dict):
+            import numpy as np
+            cols = [np.ascontiguousarray(program[k], dtype=np.float64).ravel() for k in cls.FIELDS]
+            for c in cols:
+                if c.size < turns:
+                    raise ValueError("programme has %d < %d entries" % (c.size, turns))
+            flat = np.stack([c[:turns] for c in cols], axis=1)
+            ctypes.memmove(arr, flat.ctypes.data, flat.nbytes)
+        else:
+            for i in range(int(turns)):
+                arr[i] = program[i]
+        return arr
+
+
+class Twiss(ctypes.Structure):
+    _fields_ = [("q_x", c_d), ("qp_x", c_d), ("alpha_x", c_d), ("beta_x", c_d),
+                ("q_y", c_d), ("qp_y", c_d), ("alpha_y", c_d), ("beta_y", c_d)]
+
+    @classmethod
+    def of(cls, t) -> "Twiss":
+        if isinstance(t, Twiss):
+            return t
+        get = (lambda k: t[k]) if isinstance(t, dict) else (lambda k: getattr(t, k))
+        return cls(*[float(get(k)) for k, _ in cls._fields_])
+
+
 class Moments(ctypes.Structure):
     _fields_ = [("mean_z", c_d), ("rms_z", c_d), ("mean_dp", c_d), ("rms_dp", c_d),
                 ("emit_rms", c_d)]
@@ -127,6 +179,12 @@ _SIGS = {
     "ltrk_track_f64": ([c_vp, c_vp, c_i64, c_i64, P(Ring), ctypes.c_int, c_vp, c_vp], ctypes.c_int),
     "ltrk_track_f32c": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, P(Ring), ctypes.c_int, c_vp, c_vp],
                         ctypes.c_int),
+    "ltrk_track_rf2_f64": ([c_vp, c_vp, c_i64, c_i64, P(Rf2), ctypes.c_int, c_vp, c_vp],
+                           ctypes.c_int),
+    "ltrk_track_program_f64": ([c_vp, c_vp, c_i64, c_i64, P(Rf2), P(RfTurn), ctypes.c_int, c_vp,
+                                c_vp], ctypes.c_int),
+    "ltrk_track_6d_f64": ([c_vp] * 6 + [c_i64, c_i64, P(Rf2), P(Twiss), ctypes.c_int, c_vp, c_vp],
+                          ctypes.c_int),
     "ltrk_moments_f64": ([c_vp, c_vp, c_i64, c_vp, c_vp], ctypes.c_int),
     "ltrk_moments_f32c": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp], ctypes.c_int),
     "ltrk_track_batched": ([P(Bunch), ctypes.c_int, c_i64, ctypes.c_int, ctypes.c_int, c_vp],
@@ -245,6 +303,52 @@ def ltrk_track_f32c(z, dp, z_comp, dp_comp, turns: int, ring, integrator="leapfr
                                 _dev_ptr(z_comp, f, n, "z_comp"), _dev_ptr(dp_comp, f, n, "dp_comp"),
                                 n, int(turns), ctypes.byref(Ring.of(ring)), _integ(integrator),
                                 _mom_ptr(moments, int(turns)), _stream(stream)))
+
+
+def ltrk_track_rf2_f64(z, dp, turns: int, rf2, integrator="leapfrog", moments=None,
+                       stream=None):
+    """Track through the extended map (double-harmonic RF, phase offsets, slip
+    factor expanded in dp). rf2: ring fields plus phi1_rad, harmonic2,
+    voltage2_V, phi2_rad, eta1, eta2."""
+    import torch
+    n = z.numel()
+    _check(_lib.ltrk_track_rf2_f64(_dev_ptr(z, torch.float64, None, "z"),
+                                   _dev_ptr(dp, torch.float64, n, "dp"), n, int(turns),
+                                   ctypes.byref(Rf2.of(rf2)), _integ(integrator),
+                                   _mom_ptr(moments, int(turns)), _stream(stream)))
+
+
+def ltrk_track_program_f64(z, dp, turns: int, rf2, program, integrator="leapfrog",
+                           moments=None, stream=None):
+    """Track through the extended map with per-turn RF settings and reference
+    momentum. rf2: fixed parameters (its p0c_eV is the momentum before the
+    first turn); program: dict of per-turn arrays (RfTurn.FIELDS, entry t for
+    turn t, p0c_eV the momentum after it) or an RfTurn array."""
+    import torch
+    n = z.numel()
+    prog = RfTurn.array(program, int(turns))
+    _check(_lib.ltrk_track_program_f64(_dev_ptr(z, torch.float64, None, "z"),
+                                       _dev_ptr(dp, torch.float64, n, "dp"), n, int(turns),
+                                       ctypes.byref(Rf2.of(rf2)), prog, _integ(integrator),
+                                       _mom_ptr(moments, int(turns)), _stream(stream)))
+
+
+def ltrk_track_6d_f64(z, dp, x, xp, y, yp, turns: int, rf2, twiss, integrator="leapfrog",
+                      moments=None, stream=None):
+    """Track a 6-D state (transverse Twiss rotation with chromatic phase, then
+    the extended longitudinal step, per turn). twiss: q_x, qp_x, alpha_x,
+    beta_x, q_y, qp_y, alpha_y, beta_y. moments: [turns, 3, 5] float64 or
+    None (rows of (z, dp), (x, xp), (y, yp) after each turn)."""
+    import torch
+    n = z.numel()
+    f = torch.float64
+    mom = _mom_ptr(moments, 3 * int(turns))
+    _check(_lib.ltrk_track_6d_f64(_dev_ptr(z, f, None, "z"), _dev_ptr(dp, f, n, "dp"),
+                                  _dev_ptr(x, f, n, "x"), _dev_ptr(xp, f, n, "xp"),
+                                  _dev_ptr(y, f, n, "y"), _dev_ptr(yp, f, n, "yp"), n,
+                                  int(turns), ctypes.byref(Rf2.of(rf2)),
+                                  ctypes.byref(Twiss.of(twiss)), _integ(integrator), mom,
+                                  _stream(stream)))
 
 
 def ltrk_moments_f64(z, dp, out, stream=None):

@@ -1,4 +1,7 @@
-// HIP kernels of libltrk for gfx950 (CDNA4).
+// HIP kernels of libltrk for gfx950 (CDNA4): the single-harmonic map (FP64
+// and FP32 + Kahan), batched and engine launches, and the moment finalize.
+// The extended map, RF programmes and the 6-D map are in kernels_ext.hip;
+// the shared wave-tile machinery is in wave.h.
 //
 // The hot path is the per-particle turn map of Oeftiger 2014, section 1.1.2
 // (drift z -= w eta C delta, kick delta += w A sin(2 pi h z / C)) applied by
@@ -17,8 +20,8 @@
 //     (ILP for the FP64 VALU, which is the bound once turns are fused);
 //   - per-turn moment sums: each lane sums its P particles, the 5 lane sums
 //     of a turn go to a per-wave LDS row buffer, and every kFlushTurns turns
-//     the 15 rows are reduced by 4 lanes each and written as one double per
-//     (turn, moment, wave) to HBM. No block barrier and no atomics are used,
+//     the 30 rows (6 turns x 5 sums) are reduced by 2 lanes each and written
+//     as one double per (turn, moment, wave) to HBM. No block barrier and no atomics are used,
 //     so waves never wait on each other and every sum has a fixed order;
 //   - a separate finalize kernel adds the per-wave sums of each turn in a
 //     fixed order that depends only on the number of waves, so the moments
@@ -35,51 +38,19 @@
 // All arithmetic is written with explicit fma(); the library is compiled with
 // -ffp-contract=off so the rounding of every operation is fixed by the source.
 
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "kernels.h"
 #include "ltrk_device.h"
+#include "wave.h"
 
 namespace ltrk {
 
 // ---------------------------------------------------------------------------
-// Elementary operations
+// FP32 + Kahan helper
 
-// Kick terms for phase u (in half revolutions): returns r' and p with
-// r' * p = (scale) * sin(pi u), where q holds scale * kSinPiCoeff. n = rint(u),
-// r = u - n is exact (|r| <= 1/2), p = sum_j q[j] r^2j, and the sign (-1)^n is
-// applied to r: for |n| < 2^52 the parity of n is the last mantissa bit of
-// |n| + 2^52; larger |u| has r = 0, where the sign is moot.
-struct KickTerms {
-  double r, p;
-};
-
-__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
-  const double n = __builtin_rint(u);
-  const double r = u - n;
-  const double s = r * r;
-  double p = q[kSinTerms - 1];
-#pragma unroll
-  for (int j = kSinTerms - 2; j >= 0; --j) p = __builtin_fma(p, s, q[j]);
-  const double t = __builtin_fabs(n) + 0x1p52;
-  const uint64_t odd = (__builtin_bit_cast(uint64_t, t) & 1ull) << 63;
-  return KickTerms{__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd), p};
-}
-
-// scale * sin(pi u) as one product.
-__device__ __forceinline__ double scaled_sin(double u, const double* __restrict__ q) {
-  const KickTerms k = kick_terms(u, q);
-  return k.r * k.p;
-}
-
-// delta + scale * sin(pi u) with the last product fused into the update.
-__device__ __forceinline__ double kicked(double d, double u, const double* __restrict__ q) {
-  const KickTerms k = kick_terms(u, q);
-  return __builtin_fma(k.r, k.p, d);
-}
-
-// Kahan-compensated x += inc with the running compensation c (value = x - c).
 __device__ __forceinline__ void kahan_add(float& x, float& c, float inc) {
   const float y = inc - c;
   const float t = x + y;
@@ -171,121 +142,15 @@ __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float
   }
 }
 
-// ---------------------------------------------------------------------------
-// Moment sums
-
-struct Sums {
-  double z, zz, d, dd, zd;
+// Turn functor of the single-harmonic map for wave_f64.
+template <int INTEG>
+struct SingleRf {
+  const Coeffs& c;
+  __device__ __forceinline__ int at(int) const { return 0; }
+  __device__ __forceinline__ void operator()(int, double& z, double& d) const {
+    turn_f64<INTEG>(z, d, c);
+  }
 };
-
-__device__ __forceinline__ void accumulate(Sums& s, double z, double d) {
-  s.z += z;
-  s.zz = __builtin_fma(z, z, s.zz);
-  s.d += d;
-  s.dd = __builtin_fma(d, d, s.dd);
-  s.zd = __builtin_fma(z, d, s.zd);
-}
-
-// Wave-scope ordering of LDS accesses (all lanes of one wave; no block barrier).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void stage_sums(double* buf, int j, const Sums& s, int lane) {
-  double* r = buf + j * 5 * kRowStride + lane;
-  r[0 * kRowStride] = s.z;
-  r[1 * kRowStride] = s.zz;
-  r[2 * kRowStride] = s.d;
-  r[3 * kRowStride] = s.dd;
-  r[4 * kRowStride] = s.zd;
-}
-
-// Reduce `rows` staged LDS rows of 64 lane values each; row r goes to
-// out[r * stride]. Row r is summed by kLanesPerRow lanes (r, r + R, r + 2R, ...
-// with R = 64 / kLanesPerRow), each adding its 64 / kLanesPerRow consecutive
-// values in a pairwise tree; the partial sums are then combined by xor
-// shuffles over R, 2R, ..., which gives every lane of the row the same total.
-__device__ __forceinline__ void flush_rows(const double* buf, int rows, double* out,
-                                           int64_t stride, int lane) {
-  constexpr int R = kWave / kLanesPerRow;   // row slots per flush
-  constexpr int V = kWave / kLanesPerRow;   // values per lane
-  static_assert(kFlushTurns * 5 <= R, "flush rows exceed row slots");
-  const int row = lane & (R - 1);
-  const int part = lane / R;
-  double part_sum = 0.0;
-  if (row < rows) {
-    const double2* src = reinterpret_cast<const double2*>(buf + row * kRowStride + part * V);
-    double q[V / 2];
-#pragma unroll
-    for (int j = 0; j < V / 2; ++j) {
-      const double2 v = src[j];
-      q[j] = v.x + v.y;
-    }
-#pragma unroll
-    for (int w = V / 4; w >= 1; w >>= 1) {
-#pragma unroll
-      for (int j = 0; j < w; ++j) q[j] = q[2 * j] + q[2 * j + 1];
-    }
-    part_sum = q[0];
-  }
-  double x = part_sum;
-#pragma unroll
-  for (int off = R; off < kWave; off <<= 1) x = x + __shfl_xor(x, off);
-  if (part == 0 && row < rows) out[static_cast<int64_t>(row) * stride] = x;
-}
-
-// ---------------------------------------------------------------------------
-// One wave tile for `turns` turns.
-
-template <int INTEG, int P, bool MOM>
-__device__ __forceinline__ void wave_f64(const BunchDev& b, int64_t w, int turns, int row0,
-                                         double* buf) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t first = w * static_cast<int64_t>(kWave * P) + lane;
-  double* __restrict__ zp = static_cast<double*>(b.z);
-  double* __restrict__ dpp = static_cast<double*>(b.dp);
-  double z[P], d[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int64_t i = first + static_cast<int64_t>(p) * kWave;
-    z[p] = 0.0;
-    d[p] = 0.0;
-    if (i < b.n) {
-      z[p] = __builtin_nontemporal_load(&zp[i]);
-      d[p] = __builtin_nontemporal_load(&dpp[i]);
-    }
-  }
-  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  for (int t = 0; t < turns; t += kFlushTurns) {
-    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
-    for (int j = 0; j < nb; ++j) {
-      Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        turn_f64<INTEG>(z[p], d[p], b.c);
-        if constexpr (MOM) accumulate(s, z[p], d[p]);
-      }
-      if constexpr (MOM) stage_sums(buf, j, s, lane);
-    }
-    if constexpr (MOM) {
-      wave_sync();
-      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
-      wave_sync();
-    }
-  }
-  if constexpr (INTEG != kMeasureOnly) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int64_t i = first + static_cast<int64_t>(p) * kWave;
-      if (i < b.n) {
-        __builtin_nontemporal_store(z[p], &zp[i]);
-        __builtin_nontemporal_store(d[p], &dpp[i]);
-      }
-    }
-  }
-}
 
 template <int INTEG, int P, bool MOM>
 __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turns, int row0,
@@ -346,10 +211,11 @@ template <int INTEG, int DT, int P>
 __device__ __forceinline__ void run_wave(const BunchDev& b, int64_t w, int turns, int row0,
                                          double* buf) {
   if constexpr (DT == kF64) {
+    const SingleRf<INTEG> turn{b.c};
     if (b.partials)
-      wave_f64<INTEG, P, true>(b, w, turns, row0, buf);
+      wave_f64<INTEG, P, true, false>(b, turn, w, turns, row0, buf);
     else
-      wave_f64<INTEG, P, false>(b, w, turns, row0, buf);
+      wave_f64<INTEG, P, false, false>(b, turn, w, turns, row0, buf);
   } else {
     if (b.partials)
       wave_f32c<INTEG, P, true>(b, w, turns, row0, buf);
@@ -362,12 +228,6 @@ __device__ __forceinline__ void run_wave(const BunchDev& b, int64_t w, int turns
 // Kernels
 
 // One bunch; block b covers wave tiles [b * wpb, (b+1) * wpb).
-// LDS doubles per wave for a launch of `turns` turns (the row buffer holds at
-// most kFlushTurns turns of 5 sums).
-__host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
-  return (turns < kFlushTurns ? (turns > 0 ? turns : 1) : kFlushTurns) * 5 * kRowStride;
-}
-
 template <int INTEG, int DT, int P>
 __global__ __launch_bounds__(kMaxBlock) void k_track_single(BunchDev b, int32_t row0) {
   extern __shared__ double lds[];
@@ -377,6 +237,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_track_single(BunchDev b, int32_t 
   run_wave<INTEG, DT, P>(b, w, b.turns, row0, lds + wib * lds_doubles_per_wave(b.turns));
 }
 
+// One bunch through the extended map (FP64 state).
 // Many bunches, one scheme and precision; block -> tiles[blockIdx.x].
 template <int INTEG, int DT, int P>
 __global__ __launch_bounds__(kMaxBlock) void k_track_tiles(const BunchDev* __restrict__ bunches,
@@ -420,10 +281,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_track_mixed(const BunchDev* __res
 // l, l + 64, ... in order, then a xor butterfly over the 64 lanes (every lane
 // ends with the same, fixed-order total). `cols` are wave tiles (one stage)
 // or group sums (second stage).
-__device__ __forceinline__ void finalize_row(const double* __restrict__ base, int64_t cols,
-                                             int64_t n, ltrk_moments* out, int row) {
+// `p` points at one row's 5 x cols sums, the result goes to *out.
+__device__ __forceinline__ void finalize_row(const double* __restrict__ p, int64_t cols,
+                                             int64_t n, ltrk_moments* out) {
   const int lane = threadIdx.x & (kWave - 1);
-  const double* p = base + static_cast<int64_t>(row) * 5 * cols;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t w = lane; w < cols; w += kWave) {
 #pragma unroll
@@ -450,7 +311,7 @@ __device__ __forceinline__ void finalize_row(const double* __restrict__ base, in
     o.mean_dp = md;
     o.rms_dp = __builtin_sqrt(vd);
     o.emit_rms = __builtin_sqrt(e2 > 0.0 ? e2 : 0.0);
-    out[row] = o;
+    *out = o;
   }
 }
 
@@ -464,7 +325,7 @@ __device__ __forceinline__ void group_sum(const FinalizeDev& f, int row, int64_t
   const int lane = tid & (kWave - 1);
   const int wave = tid >> 6;
   const int64_t W = f.waves;
-  const double* p = f.partials + static_cast<int64_t>(row) * 5 * W;
+  const double* p = f.partials + static_cast<int64_t>(row) * 5 * planes_of(f) * W;
   const int64_t w0 = g * kGroupWaves;
   const int64_t w1 = w0 + kGroupWaves < W ? w0 + kGroupWaves : W;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -501,12 +362,16 @@ __global__ __launch_bounds__(256) void k_group_multi(const FinalizeDev* __restri
   group_sum(f, row, blockIdx.x);
 }
 
+// Row `row` of one bunch (or plane) into out[row * planes].
 __device__ __forceinline__ void finalize_bunch_row(const FinalizeDev& f, ltrk_moments* out,
                                                    int row) {
+  const int planes = planes_of(f);
   if (f.groups > 1)
-    finalize_row(f.stage, f.groups, f.n, out, row);
+    finalize_row(f.stage + static_cast<int64_t>(row) * 5 * f.groups, f.groups, f.n,
+                 out + static_cast<int64_t>(row) * planes);
   else
-    finalize_row(f.partials, f.waves, f.n, out, row);
+    finalize_row(f.partials + static_cast<int64_t>(row) * 5 * planes * f.waves, f.waves, f.n,
+                 out + static_cast<int64_t>(row) * planes);
 }
 
 __global__ __launch_bounds__(256) void k_finalize_single(FinalizeDev f) {
@@ -515,13 +380,13 @@ __global__ __launch_bounds__(256) void k_finalize_single(FinalizeDev f) {
 }
 
 // blockIdx.y selects the bunch; rows [0, min(rows, f.rows)) are reduced and
-// written to f.out[out_row0 + row].
+// written to f.out[(out_row0 + row) * planes].
 __global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeDev* __restrict__ fs,
                                                         int32_t rows, int64_t out_row0) {
   const FinalizeDev f = fs[blockIdx.y];
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (f.out == nullptr || row >= rows || row >= f.rows) return;
-  finalize_bunch_row(f, f.out + out_row0, row);
+  finalize_bunch_row(f, f.out + out_row0 * planes_of(f), row);
 }
 
 __global__ void k_fill_nan(ltrk_moments* out, int64_t rows) {
@@ -545,16 +410,6 @@ __global__ void k_fill_probe(double* z, double* dp, int64_t n) {
 // Host-side launchers
 
 namespace {
-
-int ppl_index(int ppl) {
-  switch (ppl) {
-    case 1: return 0;
-    case 2: return 1;
-    case 4: return 2;
-    case 8: return 3;
-    default: return -1;
-  }
-}
 
 using SingleFn = void (*)(BunchDev, int32_t);
 using TilesFn = void (*)(const BunchDev*, const TileDev*, int32_t, int32_t);
@@ -606,12 +461,6 @@ MixedFn pick_mixed(int pi) {
     case 2: return k_track_mixed<4>;
     default: return k_track_mixed<8>;
   }
-}
-
-size_t lds_bytes(int block, bool moments, int turns) {
-  return moments ? static_cast<size_t>(block / kWave) * lds_doubles_per_wave(turns) *
-                       sizeof(double)
-                 : 0;
 }
 
 }  // namespace

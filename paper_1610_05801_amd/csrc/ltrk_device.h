@@ -78,14 +78,21 @@ __host__ __device__ inline int64_t finalize_groups(int64_t waves) {
 
 // Finalize work: reduce rows of per-wave partial sums of one bunch.
 struct FinalizeDev {
-  const double* partials;  // [rows][5][waves]
+  const double* partials;  // [rows][planes][5][waves], at this plane
   double* stage;           // [rows][5][groups] group sums when groups > 1
   int64_t waves;
   int64_t groups;
   int64_t n;
   ltrk_moments* out;
   int32_t rows;
-  int32_t pad;
+  int32_t planes;  // planes interleaved per row (0 or 1: one; the 6-D map: 3):
+                   // partial rows are 5 * planes * waves apart, the plane's
+                   // own sums start at `partials`, and row r is written to
+                   // out[r * planes]
 };
+
+__host__ __device__ inline int planes_of(const FinalizeDev& f) {
+  return f.planes > 1 ? f.planes : 1;
+}
 
 }  // namespace ltrk

@@ -136,6 +136,187 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
   }
 }
 
+int validate_rf2(const ltrk_rf2* r) {
+  if (!r) return fail(LTRK_EINVAL, "rf2 is NULL");
+  int rc = validate_ring(&r->ring);
+  if (rc) return rc;
+  const double v[6] = {r->phi1_rad, r->harmonic2, r->voltage2_V, r->phi2_rad, r->eta1, r->eta2};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(LTRK_EINVAL, "rf2 parameter is not finite");
+  if (r->voltage2_V != 0.0 && (!(r->harmonic2 > 0.0) || std::floor(r->harmonic2) != r->harmonic2))
+    return fail(LTRK_EINVAL, "harmonic2 must be a positive integer");
+  return LTRK_OK;
+}
+
+void make_coeffs_rf2(const ltrk_rf2& r, int integrator, CoeffsRf2* c) {
+  ltrk_derived d;
+  derive(r.ring, &d);
+  const double C = r.ring.circumference_m;
+  const double eta[3] = {d.eta, r.eta1, r.eta2};
+  const double A[2] = {d.kick_amplitude,
+                       r.ring.charge_e * r.voltage2_V / (d.beta * r.ring.p0c_eV)};
+  std::memset(c, 0, sizeof(*c));
+  c->s[0] = 2.0 * r.ring.harmonic / C;
+  c->s[1] = 2.0 * r.harmonic2 / C;
+  c->u0[0] = r.phi1_rad / M_PI;
+  c->u0[1] = r.phi2_rad / M_PI;
+  c->harmonics = r.voltage2_V != 0.0 ? 2 : 1;
+  double wd[2] = {1.0, 0.0}, wk[2] = {1.0, 0.0};  // drift and kick weights (turns)
+  switch (integrator) {
+    case LTRK_LEAPFROG:
+      wd[0] = 0.5;
+      break;
+    case LTRK_RUTH4: {
+      const double th = 1.0 / (2.0 - std::cbrt(2.0));
+      wd[0] = 0.5 * th;
+      wd[1] = 0.5 * (1.0 - th);
+      wk[0] = th;
+      wk[1] = 1.0 - 2.0 * th;
+      break;
+    }
+    default:  // Euler-Cromer and RK4 (slip and force of weight 1)
+      break;
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) c->nd[i][j] = -((wd[i] * C) * eta[j]);
+  for (int i = 0; i < 2; ++i)
+    for (int h = 0; h < 2; ++h)
+      for (int j = 0; j < kSinTerms; ++j) c->kq[i][h][j] = (wk[i] * A[h]) * kSinPiCoeff[j];
+}
+
+// ---------------------------------------------------------------------------
+// RF programme: per-turn records of folded coefficients
+
+int validate_program(const ltrk_rf2* rf, const ltrk_rf_turn* prog, int64_t turns,
+                     int integrator, bool* accel, int* harmonics) {
+  int rc = validate_rf2(rf);
+  if (rc) return rc;
+  if (turns > 0 && !prog) return fail(LTRK_EINVAL, "program is NULL");
+  const double h2 = rf->harmonic2;
+  const bool h2_ok = h2 > 0.0 && std::floor(h2) == h2;
+  bool acc = false;
+  int harm = 1;
+  double before = rf->ring.p0c_eV;
+  for (int64_t t = 0; t < turns; ++t) {
+    const ltrk_rf_turn& e = prog[t];
+    const double v[5] = {e.voltage_V, e.phi1_rad, e.voltage2_V, e.phi2_rad, e.p0c_eV};
+    for (double x : v)
+      if (!std::isfinite(x))
+        return fail(LTRK_EINVAL, "programme entry %lld is not finite", (long long)t);
+    if (!(e.p0c_eV > 0.0))
+      return fail(LTRK_EINVAL, "programme entry %lld: p0c must be > 0", (long long)t);
+    if (e.voltage2_V != 0.0) {
+      if (!h2_ok)
+        return fail(LTRK_EINVAL, "programme entry %lld has voltage2 but harmonic2 is not a "
+                    "positive integer", (long long)t);
+      harm = 2;
+    }
+    if (e.p0c_eV != before) acc = true;
+    before = e.p0c_eV;
+  }
+  if (acc && integrator == LTRK_RK4)
+    return fail(LTRK_EUNSUPPORTED, "RK4 needs a constant reference momentum");
+  *accel = acc;
+  *harmonics = harm;
+  return LTRK_OK;
+}
+
+// Fill `turns` records of prog_layout(integrator) for the programme. Turn t
+// moves the reference from p_a to p_b; kick j of weight wk_j ends at the
+// reference p_a + W_j (p_b - p_a) (W_j: kick weights summed up to j, the last
+// one exactly p_b), and drift j runs at the reference current before it. The
+// constants use derive() on the ring at that momentum, so a constant
+// programme gives the coefficients of make_coeffs_rf2 bit for bit.
+void fill_program(const ltrk_rf2& rf, const ltrk_rf_turn* prog, int64_t turns, int integrator,
+                  double* out) {
+  const ProgLayout L = prog_layout(integrator);
+  const double th = 1.0 / (2.0 - std::cbrt(2.0));
+  double wd[4] = {1.0, 0.0, 0.0, 0.0}, wk[3] = {1.0, 0.0, 0.0}, W[3] = {1.0, 0.0, 0.0};
+  int dref[4] = {0, 0, 0, 0};  // reference index (0 = p_a, j+1 = after kick j) of drift j
+  if (integrator == LTRK_LEAPFROG) {
+    wd[0] = wd[1] = 0.5;
+    dref[1] = 1;
+  } else if (integrator == LTRK_RUTH4) {
+    wd[0] = wd[3] = 0.5 * th;
+    wd[1] = wd[2] = 0.5 * (1.0 - th);
+    wk[0] = wk[2] = th;
+    wk[1] = 1.0 - 2.0 * th;
+    W[0] = th;
+    W[1] = 1.0 - th;
+    W[2] = 1.0;
+    dref[1] = 1;
+    dref[2] = 2;
+    dref[3] = 3;
+  }
+  const double C = rf.ring.circumference_m;
+  const double q = rf.ring.charge_e;
+  ltrk_ring r = rf.ring;
+  ltrk_derived d;
+  double memo_p = NAN, memo_eta = 0.0, memo_beta = 0.0;
+  auto at = [&](double p) {  // (eta0, beta) at reference momentum p
+    if (p != memo_p) {
+      r.p0c_eV = p;
+      derive(r, &d);
+      memo_p = p;
+      memo_eta = d.eta;
+      memo_beta = d.beta;
+    }
+  };
+  double p_a = rf.ring.p0c_eV;
+  for (int64_t t = 0; t < turns; ++t) {
+    const ltrk_rf_turn& e = prog[t];
+    const double p_b = e.p0c_eV;
+    double pr[4];
+    pr[0] = p_a;
+    for (int j = 0; j < L.kicks; ++j) pr[j + 1] = j + 1 == L.kicks ? p_b : p_a + W[j] * (p_b - p_a);
+    at(p_a);
+    const double beta_a = memo_beta;
+    double* o = out + t * L.stride;
+    std::memset(o, 0, sizeof(double) * L.stride);
+    o[L.u0 + 0] = e.phi1_rad / M_PI;
+    o[L.u0 + 1] = e.phi2_rad / M_PI;
+    for (int j = 0; j < L.drifts; ++j) {
+      at(pr[dref[j]]);
+      o[L.nd + j] = -((wd[j] * C) * memo_eta);
+    }
+    const double V[2] = {e.voltage_V, e.voltage2_V};
+    for (int j = 0; j < L.kicks; ++j) {
+      const double p = pr[j], pn = pr[j + 1];
+      o[L.ref + 2 * j] = p / pn;
+      o[L.ref + 2 * j + 1] = (p - pn) / pn;
+      for (int h = 0; h < 2; ++h) {
+        const double A = q * V[h] / (beta_a * pn);
+        for (int k = 0; k < kSinTerms; ++k)
+          o[L.kq + (2 * j + h) * kSinTerms + k] = (wk[j] * A) * kSinPiCoeff[k];
+      }
+    }
+    p_a = p_b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 6-D map: Twiss parameters of the transverse planes
+
+int validate_twiss(const ltrk_twiss* t) {
+  if (!t) return fail(LTRK_EINVAL, "twiss is NULL");
+  const double v[8] = {t->q_x, t->qp_x, t->alpha_x, t->beta_x,
+                       t->q_y, t->qp_y, t->alpha_y, t->beta_y};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(LTRK_EINVAL, "twiss parameter is not finite");
+  if (!(t->beta_x > 0.0) || !(t->beta_y > 0.0)) return fail(LTRK_EINVAL, "beta must be > 0");
+  return LTRK_OK;
+}
+
+// Phase in half revolutions u = 2 frac(Q) + 2 Q' delta (the integer part of
+// the tune is dropped exactly: the rotation depends on Q modulo 1).
+void make_plane(double q, double qp, double alpha, double beta, PlaneDev* p) {
+  p->u0 = 2.0 * (q - std::floor(q));
+  p->u1 = 2.0 * qp;
+  p->alpha = alpha;
+  p->beta = beta;
+  p->neg_gamma = -((1.0 + alpha * alpha) / beta);
+}
+
 // Doubles per (row, moment) of moment scratch for a bunch of W wave tiles:
 // the per-wave sums plus, for two-stage finalizes, the group sums.
 int64_t scratch_cols(int64_t W) {
@@ -259,9 +440,20 @@ struct Scratch {
   size_t bytes = 0;
 };
 
+// Per-stream programme records: device copy, pinned staging, and an event
+// recorded after the last copy out of the staging buffer.
+struct ProgBuf {
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  double* host = nullptr;
+  size_t host_bytes = 0;
+  hipEvent_t copied = nullptr;
+};
+
 struct DeviceCtx {
   std::mutex mu;
   std::unordered_map<hipStream_t, Scratch> scratch;
+  std::unordered_map<hipStream_t, ProgBuf> progs;
   std::list<std::pair<std::string, GraphEntry>> graphs;  // most recent first
   size_t max_graphs = 32;
 };
@@ -321,6 +513,60 @@ int ensure_scratch(DeviceCtx& c, hipStream_t s, size_t bytes, void** out) {
   }
   sc.bytes = want;
   *out = sc.ptr;
+  return LTRK_OK;
+}
+
+// Staging and device buffers of at least `bytes` for stream s. Returns once
+// the staging buffer is free (its previous copy has run); the device buffer
+// is overwritten in stream order by send_program.
+int stage_program(DeviceCtx& c, hipStream_t s, size_t bytes, double** host, void** dev) {
+  ProgBuf& pb = c.progs[s];
+  hipError_t e;
+  if (!pb.copied) {
+    if ((e = hipEventCreateWithFlags(&pb.copied, hipEventDisableTiming)) != hipSuccess) {
+      pb.copied = nullptr;
+      return fail_hip(e, "programme event");
+    }
+  } else if ((e = hipEventSynchronize(pb.copied)) != hipSuccess) {
+    return fail_hip(e, "wait for the previous programme copy");
+  }
+  const size_t want = std::max(bytes, static_cast<size_t>(1) << 16);
+  if (pb.host_bytes < bytes) {
+    if (pb.host) hipHostFree(pb.host);
+    pb.host = nullptr;
+    pb.host_bytes = 0;
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&pb.host), want, hipHostMallocDefault)) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      pb.host = nullptr;
+      return fail(LTRK_ENOMEM, "pinned programme staging of %zu bytes failed", want);
+    }
+    pb.host_bytes = want;
+  }
+  if (pb.dev_bytes < bytes) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess)
+      return fail_hip(e, "hipDeviceSynchronize before programme buffer growth");
+    clear_graphs(c);  // cached graphs may name the old buffer
+    if (pb.dev) hipFree(pb.dev);
+    pb.dev = nullptr;
+    pb.dev_bytes = 0;
+    if ((e = hipMalloc(&pb.dev, want)) != hipSuccess) {
+      (void)hipGetLastError();
+      pb.dev = nullptr;
+      return fail(LTRK_ENOMEM, "programme buffer of %zu bytes failed", want);
+    }
+    pb.dev_bytes = want;
+  }
+  *host = pb.host;
+  *dev = pb.dev;
+  return LTRK_OK;
+}
+
+int send_program(DeviceCtx& c, hipStream_t s, size_t bytes) {
+  ProgBuf& pb = c.progs[s];
+  hipError_t e = hipMemcpyAsync(pb.dev, pb.host, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail_hip(e, "programme upload");
+  if ((e = hipEventRecord(pb.copied, s)) != hipSuccess) return fail_hip(e, "programme event");
   return LTRK_OK;
 }
 
@@ -404,14 +650,22 @@ int64_t chunk_rows(int64_t turns, int64_t K, int64_t cols_total, bool two_stage)
 
 static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_t turns,
                         const ltrk_ring* ring, int integrator, int dtype, ltrk_moments* mom,
-                        hipStream_t s) {
-  int rc = validate_ring(ring);
+                        hipStream_t s, const ltrk_rf2* ext = nullptr,
+                        const ltrk_rf_turn* program = nullptr, bool use_program = false) {
+  bool accel = false;
+  int harmonics = 1;
+  int rc = use_program ? validate_program(ext, program, turns, integrator, &accel, &harmonics)
+           : ext       ? validate_rf2(ext)
+                       : validate_ring(ring);
   if (rc) return rc;
+  if (ext) ring = &ext->ring;
   if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
   if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
   if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
   if (turns > INT32_MAX) return fail(LTRK_EINVAL, "turns must be < 2^31");
   if (turns == 0) return LTRK_OK;
+  if (use_program && stream_capturing(s))
+    return fail(LTRK_EUNSUPPORTED, "the programme upload cannot be captured into a graph");
   if (mom && (rc = check_device_range(mom, static_cast<size_t>(turns) * sizeof(ltrk_moments),
                                       "moments")))
     return rc;
@@ -444,6 +698,10 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   b.dtype = dtype;
   b.active = 1;
   make_coeffs(*ring, integrator, &b.c);
+  CoeffsRf2 ce;
+  std::memset(&ce, 0, sizeof(ce));
+  if (ext) make_coeffs_rf2(*ext, integrator, &ce);
+  if (use_program) ce.harmonics = harmonics;
 
   DeviceCtx& c = ctx_for(dev);
   std::lock_guard<std::mutex> lock(c.mu);
@@ -461,9 +719,24 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       return rc;
   }
 
+  void* prog_dev = nullptr;
+  if (use_program) {
+    const size_t stride = static_cast<size_t>(prog_layout(integrator).stride);
+    const size_t bytes = static_cast<size_t>(turns) * stride * sizeof(double);
+    double* host = nullptr;
+    if ((rc = stage_program(c, s, bytes, &host, &prog_dev))) return rc;
+    fill_program(*ext, program, turns, integrator, host);
+    if ((rc = send_program(c, s, bytes))) return rc;
+  }
+
   std::string key;
-  key_add(key, 1);
+  key_add(key, use_program ? 4 : ext ? 3 : 1);
   key_add(key, b);
+  if (ext) key_add(key, ce);
+  if (use_program) {
+    key_add(key, prog_dev);
+    key_add(key, accel);
+  }
   key_add(key, plan);
   key_add(key, turns);
   key_add(key, mom);
@@ -478,9 +751,21 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       bl.partials = static_cast<double*>(scratch);
       const int32_t row0 = static_cast<int32_t>(j);
       const int ppl = plan.ppl, block = plan.block;
-      seq.push_back({kTimeTrack, [bl, row0, ppl, block](hipStream_t st) {
-                       return launch_track_single(bl, row0, ppl, block, st);
-                     }});
+      const int32_t turn0 = static_cast<int32_t>(c0 + j);
+      if (use_program)
+        seq.push_back({kTimeTrack, [bl, ce, prog_dev, turn0, row0, ppl, block, accel](
+                                       hipStream_t st) {
+                         return launch_track_prog(bl, ce, static_cast<const double*>(prog_dev),
+                                                  turn0, row0, ppl, block, accel, st);
+                       }});
+      else if (ext)
+        seq.push_back({kTimeTrack, [bl, ce, row0, ppl, block](hipStream_t st) {
+                         return launch_track_rf2(bl, ce, row0, ppl, block, st);
+                       }});
+      else
+        seq.push_back({kTimeTrack, [bl, row0, ppl, block](hipStream_t st) {
+                         return launch_track_single(bl, row0, ppl, block, st);
+                       }});
     }
     if (mom) {
       FinalizeDev f;
@@ -493,6 +778,113 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       f.out = mom + c0;
       f.rows = static_cast<int32_t>(len);
       seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+    }
+  }
+  return execute(c, key, seq, s, plan.use_graph != 0);
+}
+
+// ---------------------------------------------------------------------------
+// 6-D tracking
+
+static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                    const ltrk_twiss* tw, int integrator, ltrk_moments* mom, hipStream_t s) {
+  int rc = validate_rf2(rf);
+  if (rc) return rc;
+  if ((rc = validate_twiss(tw))) return rc;
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
+  if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
+  if (turns > INT32_MAX / 3) return fail(LTRK_EINVAL, "turns must be < 2^31 / 3");
+  if (turns == 0) return LTRK_OK;
+  if (mom && (rc = check_device_range(mom, static_cast<size_t>(turns) * 3 * sizeof(ltrk_moments),
+                                      "moments")))
+    return rc;
+  if (n == 0) {
+    if (!mom) return LTRK_OK;
+    hipError_t e = launch_fill_nan(mom, 3 * turns, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "fill moments");
+  }
+  static const char* names[6] = {"z", "dp", "x", "xp", "y", "yp"};
+  for (int k = 0; k < 6; ++k)
+    if ((rc = check_device_range(arr[k], static_cast<size_t>(n) * sizeof(double), names[k])))
+      return rc;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false);
+  // six FP64 coordinates per particle: at most 4 particles per lane
+  const int ppl = std::min(plan.ppl, 4);
+
+  Bunch6Dev b;
+  std::memset(&b, 0, sizeof(b));
+  b.z = arr[0];
+  b.dp = arr[1];
+  b.x = arr[2];
+  b.xp = arr[3];
+  b.y = arr[4];
+  b.yp = arr[5];
+  b.n = n;
+  b.waves = waves_for(n, ppl);
+  b.integrator = integrator;
+  Coeffs6d c6;
+  std::memset(&c6, 0, sizeof(c6));
+  make_coeffs_rf2(*rf, integrator, &c6.rf);
+  make_plane(tw->q_x, tw->qp_x, tw->alpha_x, tw->beta_x, &c6.plane[0]);
+  make_plane(tw->q_y, tw->qp_y, tw->alpha_y, tw->beta_y, &c6.plane[1]);
+
+  DeviceCtx& c = ctx_for(dev);
+  std::lock_guard<std::mutex> lock(c.mu);
+  int64_t K = plan.turns_per_launch;
+  int64_t rows = turns;
+  void* scratch = nullptr;
+  const int64_t groups = finalize_groups(b.waves);
+  const int64_t cols = 3 * scratch_cols(b.waves);  // 3 planes of 5 sums per row
+  if (mom) {
+    rows = chunk_rows(turns, K, cols, groups > 1);
+    if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)b.waves);
+    K = std::min<int64_t>(K, rows);
+    if ((rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * cols * sizeof(double),
+                             &scratch)))
+      return rc;
+  }
+
+  std::string key;
+  key_add(key, 6);
+  key_add(key, b);
+  key_add(key, c6);
+  key_add(key, plan);
+  key_add(key, ppl);
+  key_add(key, turns);
+  key_add(key, mom);
+  key_add(key, scratch);
+
+  std::vector<Launch> seq;
+  for (int64_t c0 = 0; c0 < turns; c0 += rows) {
+    const int64_t len = std::min(rows, turns - c0);
+    for (int64_t j = 0; j < len; j += K) {
+      Bunch6Dev bl = b;
+      bl.turns = static_cast<int32_t>(std::min(K, len - j));
+      bl.partials = static_cast<double*>(scratch);
+      const int32_t row0 = static_cast<int32_t>(j);
+      const int block = plan.block;
+      seq.push_back({kTimeTrack, [bl, c6, row0, ppl, block](hipStream_t st) {
+                       return launch_track_6d(bl, c6, row0, ppl, block, st);
+                     }});
+    }
+    if (mom) {
+      double* base = static_cast<double*>(scratch);
+      for (int p = 0; p < 3; ++p) {
+        FinalizeDev f;
+        std::memset(&f, 0, sizeof(f));
+        f.partials = base + p * 5 * b.waves;
+        f.stage = base + rows * 15 * b.waves + p * rows * 5 * groups;
+        f.waves = b.waves;
+        f.groups = groups;
+        f.n = n;
+        f.out = mom + c0 * 3 + p;
+        f.rows = static_cast<int32_t>(len);
+        f.planes = 3;
+        seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+      }
     }
   }
   return execute(c, key, seq, s, plan.use_graph != 0);
@@ -763,6 +1155,12 @@ static int shutdown_all() {
     for (auto& sc : c.scratch)
       if (sc.second.ptr) hipFree(sc.second.ptr);
     c.scratch.clear();
+    for (auto& pg : c.progs) {
+      if (pg.second.dev) hipFree(pg.second.dev);
+      if (pg.second.host) hipHostFree(pg.second.host);
+      if (pg.second.copied) hipEventDestroy(pg.second.copied);
+    }
+    c.progs.clear();
   }
   g_ctx.clear();
   hipSetDevice(prev);
@@ -846,6 +1244,41 @@ int ltrk_track_f32c(float* z, float* dp, float* z_comp, float* dp_comp, int64_t 
   LTRK_GUARD({
     return track_single(z, dp, z_comp, dp_comp, n, turns, ring, integrator, LTRK_F32C, moments,
                         static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_track_rf2_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                       int integrator, ltrk_moments* moments, void* stream) {
+  LTRK_GUARD({
+    if (!rf) return fail(LTRK_EINVAL, "rf2 is NULL");
+    return track_single(z, dp, nullptr, nullptr, n, turns, &rf->ring, integrator, LTRK_F64,
+                        moments, static_cast<hipStream_t>(stream), rf);
+  })
+}
+
+int ltrk_track_program_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                           const ltrk_rf_turn* program, int integrator, ltrk_moments* moments,
+                           void* stream) {
+  LTRK_GUARD({
+    if (!rf) return fail(LTRK_EINVAL, "rf2 is NULL");
+    return track_single(z, dp, nullptr, nullptr, n, turns, &rf->ring, integrator, LTRK_F64,
+                        moments, static_cast<hipStream_t>(stream), rf, program, true);
+  })
+}
+
+int ltrk_track_6d_f64(double* z, double* dp, double* x, double* xp, double* y, double* yp,
+                      int64_t n, int64_t turns, const ltrk_rf2* rf, const ltrk_twiss* twiss,
+                      int integrator, ltrk_moments* moments, void* stream) {
+  LTRK_GUARD({
+    double* arr[6];
+    arr[0] = z;
+    arr[1] = dp;
+    arr[2] = x;
+    arr[3] = xp;
+    arr[4] = y;
+    arr[5] = yp;
+    return track_6d(arr, n, turns, rf, twiss, integrator, moments,
+                    static_cast<hipStream_t>(stream));
   })
 }
 

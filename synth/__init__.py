@@ -22,6 +22,18 @@ import numpy as np
 SPS_RING = dict(circumference_m=6911.0, harmonic=4620.0, voltage_V=2.0e6,
                 p0c_eV=26.0e9, mass_eV=0.938e9, gamma_t=22.77, charge_e=1.0)
 
+# Extended-map workload: the same ring with a second RF system at twice the
+# harmonic and a quarter of the voltage in counter-phase (bunch-lengthening
+# double RF), and slip factor eta0 + eta1 dp + eta2 dp^2 with eta0 ~ 6.29e-4
+# the ring's own value at 26 GeV.
+SPS_DOUBLE_RF = dict(SPS_RING, phi1_rad=0.0, harmonic2=9240.0, voltage2_V=0.5e6,
+                     phi2_rad=math.pi, eta1=2.5e-4, eta2=-1.9e-2)
+
+# Transverse optics of the 6-D workload at the observation point: SPS-like
+# tunes, chromaticities (tune shift per unit dp) and Twiss parameters (m).
+SPS_TWISS = dict(q_x=20.13, qp_x=1.5, alpha_x=0.7, beta_x=42.0,
+                 q_y=20.18, qp_y=-2.5, alpha_y=-1.1, beta_y=87.0)
+
 SIGMA_Z = 0.23      # metres
 SIGMA_DP = 1.0e-3   # relative momentum deviation
 

@@ -127,3 +127,81 @@ def test_strerror_and_plans():
 def test_engine_footprint():
     assert ltrk.ltrk_engine_footprint(1000, 100) == 16128 + 4096
     assert ltrk.ltrk_engine_footprint(10_000_000, 100_000) == 160_000_000 + 4_000_000
+
+
+def test_rf2_validation_before_any_launch():
+    lib = _raw()
+    f = lib.ltrk_track_rf2_f64
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.POINTER(ltrk.Rf2), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    good = dict(SPS_RING, phi1_rad=0.1, harmonic2=9240.0, voltage2_V=1e6, phi2_rad=3.1,
+                eta1=1e-4, eta2=-1e-2)
+    assert f(None, None, 0, 0, ctypes.byref(ltrk.Rf2.of(good)), 1, None, None) == 0
+    for key, val in [("harmonic2", 9240.5), ("harmonic2", 0.0), ("phi2_rad", float("nan")),
+                     ("eta1", float("inf")), ("harmonic", -3.0)]:
+        bad = ltrk.Rf2.of(dict(good, **{key: val}))
+        assert f(None, None, 0, 0, ctypes.byref(bad), 1, None, None) == ltrk.LTRK_EINVAL, key
+    # no second harmonic: its harmonic number is not used
+    ok = ltrk.Rf2.of(dict(good, voltage2_V=0.0, harmonic2=0.0))
+    assert f(None, None, 0, 0, ctypes.byref(ok), 1, None, None) == 0
+    assert f(None, None, 0, 0, None, 1, None, None) == ltrk.LTRK_EINVAL
+
+
+def _programme(turns, **over):
+    arr = (ltrk.RfTurn * turns)()
+    for i in range(turns):
+        vals = dict(voltage_V=2e6, phi1_rad=0.0, voltage2_V=0.0, phi2_rad=0.0,
+                    p0c_eV=SPS_RING["p0c_eV"])
+        vals.update(over)
+        arr[i] = ltrk.RfTurn(**vals)
+    return arr
+
+
+def test_programme_validation_before_any_launch():
+    lib = _raw()
+    f = lib.ltrk_track_program_f64
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.POINTER(ltrk.Rf2), ctypes.POINTER(ltrk.RfTurn), ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    rf = ltrk.Rf2.of(dict(SPS_RING, phi1_rad=0.0, harmonic2=9240.0, voltage2_V=0.0,
+                          phi2_rad=0.0, eta1=0.0, eta2=0.0))
+    ok = _programme(4)
+    assert f(None, None, 0, 4, ctypes.byref(rf), ok, 1, None, None) == 0
+    for over in (dict(p0c_eV=0.0), dict(voltage_V=float("nan")), dict(phi2_rad=float("inf"))):
+        assert f(None, None, 0, 4, ctypes.byref(rf), _programme(4, **over), 1, None,
+                 None) == ltrk.LTRK_EINVAL, over
+    assert f(None, None, 0, 4, ctypes.byref(rf), None, 1, None, None) == ltrk.LTRK_EINVAL
+    # a second harmonic needs an integer harmonic2
+    bad_h2 = ltrk.Rf2.of(dict(SPS_RING, phi1_rad=0.0, harmonic2=0.5, voltage2_V=0.0,
+                              phi2_rad=0.0, eta1=0.0, eta2=0.0))
+    assert f(None, None, 0, 4, ctypes.byref(bad_h2), _programme(4, voltage2_V=1e5), 1, None,
+             None) == ltrk.LTRK_EINVAL
+    assert f(None, None, 0, 4, ctypes.byref(bad_h2), ok, 1, None, None) == 0
+    # RK4 supports constant momentum only
+    ramp = _programme(4)
+    ramp[2].p0c_eV = SPS_RING["p0c_eV"] * 1.001
+    assert f(None, None, 0, 4, ctypes.byref(rf), ramp, 3, None, None) == ltrk.LTRK_EUNSUPPORTED
+    assert f(None, None, 0, 4, ctypes.byref(rf), ok, 3, None, None) == 0
+    assert f(None, None, 0, 4, ctypes.byref(rf), ramp, 2, None, None) == 0
+
+
+def test_6d_validation_before_any_launch():
+    lib = _raw()
+    f = lib.ltrk_track_6d_f64
+    f.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ltrk.Rf2),
+                                          ctypes.POINTER(ltrk.Twiss), ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]
+    rf = ltrk.Rf2.of(dict(SPS_RING, phi1_rad=0.0, harmonic2=9240.0, voltage2_V=0.0,
+                          phi2_rad=0.0, eta1=0.0, eta2=0.0))
+    tw = dict(q_x=20.13, qp_x=1.0, alpha_x=0.5, beta_x=40.0, q_y=20.18, qp_y=-1.0,
+              alpha_y=-0.5, beta_y=60.0)
+    nul = [None] * 6
+    assert f(*nul, 0, 0, ctypes.byref(rf), ctypes.byref(ltrk.Twiss.of(tw)), 1, None, None) == 0
+    for key, val in [("beta_x", 0.0), ("beta_y", -1.0), ("qp_x", float("nan")),
+                     ("alpha_y", float("inf"))]:
+        bad = ltrk.Twiss.of(dict(tw, **{key: val}))
+        assert f(*nul, 0, 0, ctypes.byref(rf), ctypes.byref(bad), 1, None,
+                 None) == ltrk.LTRK_EINVAL, key
+    assert f(*nul, 0, 0, ctypes.byref(rf), None, 1, None, None) == ltrk.LTRK_EINVAL
+    assert f(*nul, 10, 5, ctypes.byref(rf), ctypes.byref(ltrk.Twiss.of(tw)), 1, None,
+             None) == ltrk.LTRK_EINVAL  # NULL state arrays

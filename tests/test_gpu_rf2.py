@@ -1,0 +1,107 @@
+"""Extended map on the GPU (double-harmonic RF with phase offsets, slip factor
+eta0 + eta1 dp + eta2 dp^2) through the C ABI, against the oracle's extended
+map.
+
+Per-particle tolerance from the arithmetic: both sides commit a few units of
+rounding u = 2^-53 per turn (the sine polynomial against libm, fused against
+separate multiply-adds), and a difference made at some turn grows by at most
+the particle's own sensitivity by the end. That sensitivity is measured with
+the oracle alone (relative perturbations of 1e-13 in z and in dp, worst of the
+two), so the bound is e_i <= 8 u turns max(amp_i, 1). In both configurations
+below every particle stays inside its bucket and amp_i <= 65 after 1e3 turns.
+Moments: 1e-10 relative, as for the single-harmonic map."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import SPS_RING, gaussian_bunch
+from tests._parity import moment_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+C0 = oracle.derive(SPS_RING)
+H1 = SPS_RING["harmonic"]
+BLM = dict(SPS_RING, phi1_rad=0.0, harmonic2=2 * H1, voltage2_V=SPS_RING["voltage_V"] / 4,
+           phi2_rad=math.pi, eta1=0.4 * C0["eta"], eta2=-30.0 * C0["eta"])
+OFFSET = dict(SPS_RING, phi1_rad=0.3, harmonic2=3 * H1, voltage2_V=-0.5e6, phi2_rad=-1.1,
+              eta1=-0.2 * C0["eta"], eta2=10.0 * C0["eta"])
+
+
+@pytest.fixture(scope="module")
+def ltrk():
+    import paper_1610_05801_amd as m
+    m.ltrk_set_plan()
+    yield m
+    m.ltrk_set_plan()
+
+
+def err(z, dp, zr, dr):
+    zb, db = C0["bucket_half_length"], C0["bucket_height"]
+    return np.hypot((z - zr) / zb, (dp - dr) / db) / np.hypot(zr / zb, dr / db)
+
+
+def tolerance(z0, dp0, turns, rf, integ):
+    eps = 1e-13
+    kw = dict(with_moments=False, threads=1 if len(z0) < 2000 else 0)
+    za, da, _ = oracle.track_rf2(z0, dp0, turns, rf, integ, **kw)
+    zb, db, _ = oracle.track_rf2(z0 * (1 + eps), dp0, turns, rf, integ, **kw)
+    zc, dc, _ = oracle.track_rf2(z0, dp0 * (1 + eps), turns, rf, integ, **kw)
+    amp = np.maximum(err(zb, db, za, da), err(zc, dc, za, da)) / eps
+    return 8 * 2.0 ** -53 * turns * np.maximum(amp, 1.0), amp
+
+
+def run(ltrk, z0, dp0, turns, rf, integ):
+    z, dp = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+    mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_track_rf2_f64(z, dp, turns, rf, integ, mom)
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy()
+
+
+@pytest.mark.parametrize("integ", ["euler_cromer", "leapfrog", "ruth4", "rk4"])
+@pytest.mark.parametrize("rf", [BLM, OFFSET], ids=["blm", "offset"])
+def test_extended_map_against_oracle(ltrk, integ, rf):
+    z0, dp0 = gaussian_bunch(1000, 0.15, 6e-4, 77)
+    z, dp, mom = run(ltrk, z0, dp0, 1000, rf, integ)
+    zr, dr, mr = oracle.track_rf2(z0, dp0, 1000, rf, integ)
+    e = err(z, dp, zr, dr)
+    tol, amp = tolerance(z0, dp0, 1000, rf, integ)
+    assert amp.max() < 1e3  # no chaotic particle in this bunch
+    assert np.all(np.isfinite(e))
+    worst = np.argmax(e / tol)
+    assert np.all(e <= tol), (e[worst], tol[worst], amp[worst])
+    print("%s: e p50 %.2e max %.2e, max e/tol %.2f" % (integ, np.median(e), e.max(),
+                                                       (e / tol).max()))
+    assert moment_error(mom, mr).max() <= 1e-10
+
+
+def test_reduces_to_single_harmonic_kernel(ltrk):
+    plain = dict(SPS_RING, phi1_rad=0.0, harmonic2=0.0, voltage2_V=0.0, phi2_rad=0.0,
+                 eta1=0.0, eta2=0.0)
+    z0, dp0 = gaussian_bunch(5000, 0.23, 1e-3, 5)
+    z, dp, mom = run(ltrk, z0, dp0, 500, plain, "leapfrog")
+    zs, ds = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+    ms = torch.empty((500, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_track_f64(zs, ds, 500, SPS_RING, "leapfrog", ms)
+    torch.cuda.synchronize()
+    assert err(z, dp, zs.cpu().numpy(), ds.cpu().numpy()).max() <= 1e-13
+    assert moment_error(mom, ms.cpu().numpy()).max() <= 1e-13
+
+
+def test_extended_paper_scale_sampled(ltrk):
+    """1e6 particles x 1e4 turns in the default launch plan, 500 sampled."""
+    n, T = 1_000_000, 10_000
+    z0, dp0 = gaussian_bunch(n, 0.15, 6e-4, 1002)
+    z, dp, mom = run(ltrk, z0, dp0, T, BLM, "leapfrog")
+    idx = np.arange(0, n, n // 500)
+    zr, dr, _ = oracle.track_rf2(z0[idx], dp0[idx], T, BLM, "leapfrog", with_moments=False,
+                                 threads=1)
+    e = err(z[idx], dp[idx], zr, dr)
+    tol, amp = tolerance(z0[idx], dp0[idx], T, BLM, "leapfrog")
+    assert np.all(e <= tol), (e / tol).max()
+    print("paper scale: e p50 %.2e max %.2e, max e/tol %.2f, amp max %.1f"
+          % (np.median(e), e.max(), (e / tol).max(), amp.max()))
+    assert moment_error(mom[-1:], oracle.moments(z, dp)[None, :]).max() <= 1e-12
