@@ -13,7 +13,8 @@ sweep), precision (FP32+Kahan vs FP64, 1e7 particles), batched (256 uneven
 bunches), serving (Poisson request stream through the engine), ksweep,
 schemes (every integrator), rf2 (double-harmonic RF, slip factor to second
 order in dp), program (per-turn RF settings and a momentum ramp), 6d
-(transverse linear map with chromaticity plus the longitudinal step).
+(transverse linear map with chromaticity plus the longitudinal step), wake
+(longitudinal resonator wake kick every turn).
 """
 from __future__ import annotations
 
@@ -620,6 +621,52 @@ def bench_6d(args):
                       "rows": rows}), flush=True)
 
 
+def bench_wake(args):
+    """Wake kick: 10^6 and 10^7 particles x 1000 turns (leap-frog, resonator,
+    256 slices), two launches per turn. The turn kernel streams the state once
+    per turn (32 B per particle-turn: the HBM roofline); the potential kernel
+    is one block. Kernel times from HIP events."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SPS_WAKE, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    T = 1000
+    rf = dict(SPS_RING, phi1_rad=0.0, harmonic2=0.0, voltage2_V=0.0, phi2_rad=0.0, eta1=0.0,
+              eta2=0.0)
+    mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+    rows = []
+    for n in (1_000_000, 10_000_000):
+        z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+        z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+        call = lambda: ltrk.ltrk_track_wake_f64(z, dp, T, rf, SPS_WAKE, "leapfrog", mom,
+                                                stream=stream)
+        with torch.cuda.stream(stream):
+            call()
+            stream.synchronize()
+            ltrk.ltrk_timing_enable(True)
+            ltrk.ltrk_timing_take()
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            tm = ltrk.ltrk_timing_take()
+            ltrk.ltrk_timing_enable(False)
+        turn_ms = tm["track_ms"] / max(tm["track_launches"], 1)
+        other_ms = tm["finalize_ms"] / max(tm["finalize_launches"], 1)
+        gbs = STATE_BYTES_PER_PARTICLE * 2 * n / (turn_ms * 1e-3) / 1e9
+        row = {"particles": n, "turns": T, "particle_turns_per_s": n * T / dt,
+               "turn_kernel_ms": turn_ms, "potential_and_finalize_ms": other_ms,
+               "hbm_GBps_algorithmic": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+               "bytes_per_particle_turn": 2 * STATE_BYTES_PER_PARTICLE}
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"workload": "wake kick: leap-frog, resonator (%g ohm, %g Hz, Q %g), "
+                      "%d slices, 1000 turns" % (SPS_WAKE["shunt"], SPS_WAKE["freq_hz"],
+                                                 SPS_WAKE["quality"], SPS_WAKE["n_slices"]),
+                      "rows": rows}), flush=True)
+
+
 def _matched_sigma_z(ltrk, ring, sigma_dp):
     d = ltrk.ltrk_derive(ring)
     return sigma_dp * d["slip_length"] / d["omega_s"]
@@ -825,7 +872,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
-                             "counters", "schemes", "rf2", "program", "6d"])
+                             "counters", "schemes", "rf2", "program", "6d", "wake"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
@@ -852,7 +899,7 @@ def main():
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
      "counters": bench_counters, "schemes": bench_schemes,
-     "rf2": bench_rf2, "program": bench_program, "6d": bench_6d}[args.workload](args)
+     "rf2": bench_rf2, "program": bench_program, "6d": bench_6d, "wake": bench_wake}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -219,6 +219,41 @@ int ltrk_track_6d_f64(double* z, double* dp, double* x, double* xp, double* y, d
                       int64_t n, int64_t turns, const ltrk_rf2* rf, const ltrk_twiss* twiss,
                       int integrator, ltrk_moments* moments, void* stream);
 
+/* Longitudinal wake: the impedance effects the paper's conclusion (section 3)
+ * names as the memory-bound next step. */
+#define LTRK_WAKE_RESONATOR 0 /* W(tau) = 2 a R e^{-a tau} (cos w' tau - (a/w') sin w' tau),
+                                 a = w_r / (2 Q), w' = sqrt(w_r^2 - a^2); W(0) = a R */
+#define LTRK_WAKE_CONSTANT 1  /* W(tau > 0) = R (V/C), W(0) = R/2: the potential is the
+                                 charge ahead */
+#define LTRK_WAKE_MAX_SLICES 4096
+
+typedef struct ltrk_wake {
+    int32_t model;        /* LTRK_WAKE_RESONATOR or LTRK_WAKE_CONSTANT */
+    int32_t n_slices;     /* 1 .. LTRK_WAKE_MAX_SLICES */
+    double shunt;         /* resonator: shunt impedance R (ohm); constant: R (V/C) */
+    double freq_hz;       /* resonator: f_r = w_r / 2 pi, > 0 */
+    double quality;       /* resonator: Q > 1/2 */
+    double intensity;     /* particles in the bunch (each macro-particle carries
+                             q e intensity / n), >= 0 */
+    double z_lo;          /* sliced range [z_lo, z_hi) in metres, z toward the head */
+    double z_hi;
+} ltrk_wake;
+
+/* The extended map (as ltrk_track_rf2_f64) with a wake kick after every
+ * step: the bunch is cut into n_slices equal slices over [z_lo, z_hi)
+ * (particles outside are neither counted nor kicked), the potential at slice
+ * centre k is V_k = Q_mp sum_{j >= k} count_j W((j - k) dz / (beta c)) with
+ * Q_mp = q e intensity / n, and a particle at z gets
+ *   delta <- delta - q V(z) / (beta p0 c),
+ * V(z) interpolated linearly between slice centres (constant beyond the first
+ * and last centre). Row t of `moments` holds the moments after turn t's kick.
+ * Same arrays and stream rules as ltrk_track_f64. EINVAL for an invalid ring,
+ * extension or wake field; EUNSUPPORTED for a stream being captured into a
+ * graph (the wake table is uploaded by a copy from reused host memory). */
+int ltrk_track_wake_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                        const ltrk_wake* wake, int integrator, ltrk_moments* moments,
+                        void* stream);
+
 /* Moments of the current state (one row) into the device row `out`. */
 int ltrk_moments_f64(const double* z, const double* dp, int64_t n, ltrk_moments* out,
                      void* stream);

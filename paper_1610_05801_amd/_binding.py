@@ -121,6 +121,25 @@ class Twiss(ctypes.Structure):
         return cls(*[float(get(k)) for k, _ in cls._fields_])
 
 
+class Wake(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("shunt", c_d),
+                ("freq_hz", c_d), ("quality", c_d), ("intensity", c_d), ("z_lo", c_d),
+                ("z_hi", c_d)]
+    MODELS = {"resonator": 0, "constant": 1}
+
+    @classmethod
+    def of(cls, w) -> "Wake":
+        if isinstance(w, Wake):
+            return w
+        get = (lambda k, dflt=None: w.get(k, dflt)) if isinstance(w, dict) else \
+            (lambda k, dflt=None: getattr(w, k, dflt))
+        model = get("model", 0)
+        model = cls.MODELS[model] if isinstance(model, str) else int(model)
+        return cls(model, int(get("n_slices")), float(get("shunt")), float(get("freq_hz", 0.0)),
+                   float(get("quality", 0.0)), float(get("intensity")), float(get("z_lo")),
+                   float(get("z_hi")))
+
+
 class Moments(ctypes.Structure):
     _fields_ = [("mean_z", c_d), ("rms_z", c_d), ("mean_dp", c_d), ("rms_dp", c_d),
                 ("emit_rms", c_d)]
@@ -185,6 +204,8 @@ _SIGS = {
                                 c_vp], ctypes.c_int),
     "ltrk_track_6d_f64": ([c_vp] * 6 + [c_i64, c_i64, P(Rf2), P(Twiss), ctypes.c_int, c_vp, c_vp],
                           ctypes.c_int),
+    "ltrk_track_wake_f64": ([c_vp, c_vp, c_i64, c_i64, P(Rf2), P(Wake), ctypes.c_int, c_vp, c_vp],
+                            ctypes.c_int),
     "ltrk_moments_f64": ([c_vp, c_vp, c_i64, c_vp, c_vp], ctypes.c_int),
     "ltrk_moments_f32c": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp], ctypes.c_int),
     "ltrk_track_batched": ([P(Bunch), ctypes.c_int, c_i64, ctypes.c_int, ctypes.c_int, c_vp],
@@ -349,6 +370,20 @@ def ltrk_track_6d_f64(z, dp, x, xp, y, yp, turns: int, rf2, twiss, integrator="l
                                   int(turns), ctypes.byref(Rf2.of(rf2)),
                                   ctypes.byref(Twiss.of(twiss)), _integ(integrator), mom,
                                   _stream(stream)))
+
+
+def ltrk_track_wake_f64(z, dp, turns: int, rf2, wake, integrator="leapfrog", moments=None,
+                        stream=None):
+    """Track through the extended map with a longitudinal wake kick after
+    every turn. wake: model ("resonator" or "constant"), n_slices, shunt,
+    freq_hz, quality, intensity, z_lo, z_hi."""
+    import torch
+    n = z.numel()
+    _check(_lib.ltrk_track_wake_f64(_dev_ptr(z, torch.float64, None, "z"),
+                                    _dev_ptr(dp, torch.float64, n, "dp"), n, int(turns),
+                                    ctypes.byref(Rf2.of(rf2)), ctypes.byref(Wake.of(wake)),
+                                    _integ(integrator), _mom_ptr(moments, int(turns)),
+                                    _stream(stream)))
 
 
 def ltrk_moments_f64(z, dp, out, stream=None):

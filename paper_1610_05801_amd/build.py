@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libltrk.so")
-SOURCES = ["kernels.hip", "kernels_ext.hip", "runtime.hip", "tune.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "kernels_ext.hip", "kernels_wake.hip", "runtime.hip", "tune.hip",
+           "engine.hip"]
 ARCH = os.environ.get("LTRK_OFFLOAD_ARCH", "gfx950")
 
 

@@ -25,6 +25,16 @@ hipError_t launch_track_prog(const BunchDev& b, const CoeffsRf2& c, const double
 // at row0 of b.partials.
 hipError_t launch_track_6d(const Bunch6Dev& b, const Coeffs6d& c, int32_t row0, int ppl,
                            int block, hipStream_t s);
+// One turn of the wake path on a fixed grid of `grid` blocks (<= kWakeMaxBlocks).
+// phase 0: map step and histogram; 1: kick from w.pot, moment row `row` (when
+// b.partials), step and histogram; 2: kick and moment row only.
+hipError_t launch_wake_turn(const BunchDev& b, const CoeffsRf2& c, const WakeDev& w, int phase,
+                            int32_t row, int ppl, int block, int grid, hipStream_t s);
+// The potential w.pot from the slice counts, which it zeroes (one block).
+hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s);
+// Zero the slice counts (start of a call; a kernel, not a memset, so a
+// captured sequence replays correctly).
+hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s);
 // Tiled launch over device tables of bunches and tiles (one scheme/precision).
 hipError_t launch_track_tiles(const BunchDev* bunches, const TileDev* tiles, int64_t ntiles,
                               int integrator, int dtype, int32_t turns, int32_t row0, int ppl,

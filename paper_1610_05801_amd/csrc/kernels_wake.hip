@@ -1,0 +1,255 @@
+// HIP kernels of libltrk for the longitudinal wake kick (gfx950): the
+// collective, memory-bound step that the paper's conclusion (section 3)
+// names next after the single-particle tracking.
+//
+// Every turn needs the line density of the whole bunch after its map step,
+// so a turn cannot stay inside one launch the way the single-particle map
+// does; it is two launches:
+//   k_wake_turn      streams the state once: applies the kick from the
+//                    previous turn's potential, adds the moment sums of that
+//                    turn, runs one step of the map and bins z into the
+//                    block's LDS slice histogram, then adds the non-zero bins
+//                    into the global slice counts (integer adds, so the
+//                    counts do not depend on the order of the blocks);
+//   k_wake_potential one block reads the counts into LDS (and zeroes them
+//                    for the next turn) and forms the causal potential
+//                    V_k = sum_{j >= k} count_j W_{j-k}, each sum split into
+//                    up to 4 consecutive j ranges added in range order.
+// k_wake_turn runs a grid-stride loop over wave tiles on a fixed grid, so a
+// wave's tiles, and with them its moment sums, do not depend on timing.
+// The state moves 32 B per particle-turn through HBM: the bound is HBM.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "ltrk_device.h"
+#include "ltrk_device_ext.h"
+#include "turn_ext.h"
+#include "wave.h"
+
+namespace ltrk {
+
+// Slice of z, or -1 outside [z_lo, z_lo + n_slices dz).
+__device__ __forceinline__ int slice_of(const WakeDev& w, double z) {
+  const double u = (z - w.z_lo) / w.dz;
+  if (!(u >= 0.0)) return -1;
+  const double f = __builtin_floor(u);
+  return f < static_cast<double>(w.n_slices) ? static_cast<int>(f) : -1;
+}
+
+// Potential at z by linear interpolation between slice centres (constant
+// beyond the first and last centre); pot is the block's LDS copy.
+__device__ __forceinline__ double potential_at(const WakeDev& w, const double* pot, double z) {
+  const double s = (z - w.z_lo) / w.dz - 0.5;
+  const int last = w.n_slices - 1;
+  if (s <= 0.0) return pot[0];
+  if (s >= static_cast<double>(last)) return pot[last];
+  const double k0 = __builtin_floor(s);
+  const double f = s - k0;
+  const int k = static_cast<int>(k0);
+  return (1.0 - f) * pot[k] + f * pot[k + 1];
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = x + __shfl_xor(x, off);
+  return x;
+}
+
+// One turn of the wake path over the bunch.
+//   KICK: delta -= kappa V(z) with V from w.pot (the previous histogram);
+//   MOM:  moment sums of the state after the kick into row `row` of
+//         b.partials ([rows][5][waves of this grid]);
+//   STEP: one step of the extended map, then the slice histogram of the new
+//         z added into w.counts.
+template <int INTEG, int H, int P, bool KICK, bool MOM, bool STEP>
+__global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c, WakeDev w,
+                                                         int32_t row) {
+  extern __shared__ double lds[];
+  double* pot = lds;                                           // n_slices doubles
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + w.n_slices);  // n_slices counters
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wpb = blockDim.x >> 6;
+  const int64_t grid_waves = static_cast<int64_t>(gridDim.x) * wpb;
+  const int64_t gw = static_cast<int64_t>(blockIdx.x) * wpb + (tid >> 6);
+  for (int k = tid; k < w.n_slices; k += blockDim.x) {
+    if constexpr (KICK) pot[k] = w.pot[k];
+    if constexpr (STEP) hist[k] = 0u;
+  }
+  __syncthreads();
+  double* __restrict__ zp = static_cast<double*>(b.z);
+  double* __restrict__ dpp = static_cast<double*>(b.dp);
+  Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+  const Rf2Src src{c};
+  for (int64_t tile = gw; tile < b.waves; tile += grid_waves) {
+    const int64_t first = tile * static_cast<int64_t>(kWave * P) + lane;
+    double z[P], d[P];
+    bool live[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t i = first + static_cast<int64_t>(p) * kWave;
+      live[p] = i < b.n;
+      z[p] = live[p] ? __builtin_nontemporal_load(&zp[i]) : 0.0;
+      d[p] = live[p] ? __builtin_nontemporal_load(&dpp[i]) : 0.0;
+    }
+    if constexpr (KICK) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (live[p] && slice_of(w, z[p]) >= 0) d[p] = d[p] - w.kappa * potential_at(w, pot, z[p]);
+    }
+    if constexpr (MOM) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) accumulate(s, z[p], d[p]);
+    }
+    if constexpr (STEP) {
+      turn_ext<INTEG, false, H, P, true>(z, d, live, c, src);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int k = live[p] ? slice_of(w, z[p]) : -1;
+        if (k >= 0) atomicAdd(&hist[k], 1u);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t i = first + static_cast<int64_t>(p) * kWave;
+      if (live[p]) {
+        if constexpr (STEP) __builtin_nontemporal_store(z[p], &zp[i]);
+        if constexpr (KICK || STEP) __builtin_nontemporal_store(d[p], &dpp[i]);
+      }
+    }
+  }
+  if constexpr (MOM) {
+    const double t[5] = {wave_sum(s.z), wave_sum(s.zz), wave_sum(s.d), wave_sum(s.dd),
+                         wave_sum(s.zd)};
+    if (lane == 0) {
+      double* out = b.partials + static_cast<int64_t>(row) * 5 * grid_waves + gw;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) out[static_cast<int64_t>(m) * grid_waves] = t[m];
+    }
+  }
+  if constexpr (STEP) {
+    __syncthreads();
+    // start each block at its own slice so that blocks finishing together
+    // add into different counters
+    const int rot = static_cast<int>((static_cast<int64_t>(blockIdx.x) * 61) % w.n_slices);
+    for (int i = tid; i < w.n_slices; i += blockDim.x) {
+      const int k = i + rot < w.n_slices ? i + rot : i + rot - w.n_slices;
+      if (hist[k] != 0u) atomicAdd(&w.counts[k], hist[k]);
+    }
+  }
+}
+
+// The causal potential V_k = sum_{j >= k} count_j W_{j-k} from the slice
+// counts (staged in LDS), which are then zeroed for the next turn; one block.
+// The sum of slice k is split into `parts` consecutive j ranges added by
+// neighbouring threads, whose partial sums are then added in range order.
+// The wake table is staged in LDS when it fits beside the counts.
+__global__ __launch_bounds__(kWakePotThreads) void k_wake_potential(WakeDev w) {
+  extern __shared__ double sh[];
+  const int ns = w.n_slices;
+  const bool stage_w = ns <= kWakeStageSlices;
+  double* cnt = sh;                           // n_slices
+  double* part = sh + ns;                     // kWakePotThreads
+  double* wl = part + kWakePotThreads;        // n_slices when staged
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    cnt[k] = static_cast<double>(w.counts[k]);
+    w.counts[k] = 0u;
+    if (stage_w) wl[k] = w.wtab[k];
+  }
+  __syncthreads();
+  const double* __restrict__ wt = stage_w ? wl : w.wtab;
+  const int parts = ns <= kWakePotThreads / 4 ? 4 : ns <= kWakePotThreads / 2 ? 2 : 1;
+  const int per_pass = kWakePotThreads / parts;
+  for (int k0 = 0; k0 < ns; k0 += per_pass) {
+    const int k = k0 + static_cast<int>(threadIdx.x) / parts;
+    const int q = static_cast<int>(threadIdx.x) % parts;
+    double v = 0.0;
+    if (k < ns) {
+      const int len = (ns - k + parts - 1) / parts;
+      const int j0 = k + q * len;
+      const int j1 = j0 + len < ns ? j0 + len : ns;
+      for (int j = j0; j < j1; ++j) v = v + cnt[j] * wt[j - k];
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    if (k < ns && q == 0) {
+      double sum = part[threadIdx.x];
+      for (int r = 1; r < parts; ++r) sum = sum + part[threadIdx.x + r];
+      w.pot[k] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_wake_zero(uint32_t* counts, int32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+
+namespace {
+
+using TurnFn = void (*)(BunchDev, CoeffsRf2, WakeDev, int32_t);
+
+template <int I, int H, bool KICK, bool MOM, bool STEP>
+TurnFn turn_fn(int ppl) {
+  return ppl == 8 ? k_wake_turn<I, H, 8, KICK, MOM, STEP> : k_wake_turn<I, H, 4, KICK, MOM, STEP>;
+}
+
+// phase 0: first turn (step only); 1: kick, moments, step; 2: last kick and moments.
+template <int I, int H>
+TurnFn by_phase(int phase, bool mom, int ppl) {
+  if (phase == 0) return turn_fn<I, H, false, false, true>(ppl);
+  if (phase == 1)
+    return mom ? turn_fn<I, H, true, true, true>(ppl) : turn_fn<I, H, true, false, true>(ppl);
+  return mom ? turn_fn<I, H, true, true, false>(ppl) : turn_fn<I, H, true, false, false>(ppl);
+}
+
+TurnFn pick_turn(int integ, int harmonics, int phase, bool mom, int ppl) {
+  const bool two = harmonics == 2;
+  switch (integ) {
+    case kEulerCromer: return two ? by_phase<kEulerCromer, 2>(phase, mom, ppl) : by_phase<kEulerCromer, 1>(phase, mom, ppl);
+    case kLeapfrog: return two ? by_phase<kLeapfrog, 2>(phase, mom, ppl) : by_phase<kLeapfrog, 1>(phase, mom, ppl);
+    case kRuth4: return two ? by_phase<kRuth4, 2>(phase, mom, ppl) : by_phase<kRuth4, 1>(phase, mom, ppl);
+    case kRk4: return two ? by_phase<kRk4, 2>(phase, mom, ppl) : by_phase<kRk4, 1>(phase, mom, ppl);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_wake_turn(const BunchDev& b, const CoeffsRf2& c, const WakeDev& w, int phase,
+                            int32_t row, int ppl, int block, int grid, hipStream_t s) {
+  if ((ppl != 4 && ppl != 8) || block <= 0 || block > kMaxBlock || block % kWave != 0 ||
+      grid <= 0 || grid > kWakeMaxBlocks || phase < 0 || phase > 2 || w.n_slices < 1 ||
+      w.n_slices > kWakeMaxSlices)
+    return hipErrorInvalidValue;
+  const bool mom = b.partials != nullptr;
+  TurnFn fn = pick_turn(b.integrator, c.harmonics, phase, mom, ppl);
+  if (!fn) return hipErrorInvalidValue;
+  const size_t lds = static_cast<size_t>(w.n_slices) * (sizeof(double) + sizeof(uint32_t));
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(grid)), dim3(block), lds, s, b, c, w, row);
+  return hipGetLastError();
+}
+
+hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s) {
+  if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
+  const size_t doubles = static_cast<size_t>(w.n_slices) + kWakePotThreads +
+                        (w.n_slices <= kWakeStageSlices ? w.n_slices : 0);
+  hipLaunchKernelGGL(k_wake_potential, dim3(1), dim3(kWakePotThreads), doubles * sizeof(double),
+                     s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s) {
+  if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_wake_zero, dim3((w.n_slices + 255) / 256), dim3(256), 0, s, w.counts,
+                     w.n_slices);
+  return hipGetLastError();
+}
+
+}  // namespace ltrk

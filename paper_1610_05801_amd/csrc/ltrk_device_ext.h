@@ -74,4 +74,23 @@ __host__ __device__ inline int lds_doubles_per_wave_6d(int turns) {
   return (turns < kFlushTurns6d ? (turns > 0 ? turns : 1) : kFlushTurns6d) * 15 * kRowStride;
 }
 
+// Longitudinal wake kick: uniform slices over [z_lo, z_lo + n_slices dz),
+// the wake at the lags between slice centres, the slice counts of the last
+// map step and the potential at the slice centres.
+constexpr int kWakeMaxSlices = 4096;
+constexpr int kWakeMaxBlocks = 1024;
+constexpr int kWakePotThreads = 1024;   // block of the potential kernel
+constexpr int kWakeStageSlices = 2048;  // wake table staged in LDS up to this many slices
+
+struct WakeDev {
+  double z_lo;
+  double dz;
+  double kappa;          // q Q_mp / (beta p0 c): delta kick per volt of potential
+  const double* wtab;    // [n_slices] W(m dz / (beta c)), W(0) half the limit
+  uint32_t* counts;      // [n_slices] counts of the last map step (zero between turns)
+  double* pot;           // [n_slices] potential of the last counts
+  int32_t n_slices;
+  int32_t pad;
+};
+
 }  // namespace ltrk

@@ -295,6 +295,58 @@ void fill_program(const ltrk_rf2& rf, const ltrk_rf_turn* prog, int64_t turns, i
 }
 
 // ---------------------------------------------------------------------------
+// Wake kick: validation and the wake at the lags between slice centres
+
+int validate_wake(const ltrk_wake* w) {
+  if (!w) return fail(LTRK_EINVAL, "wake is NULL");
+  const double v[6] = {w->shunt, w->freq_hz, w->quality, w->intensity, w->z_lo, w->z_hi};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(LTRK_EINVAL, "wake parameter is not finite");
+  if (w->model != LTRK_WAKE_RESONATOR && w->model != LTRK_WAKE_CONSTANT)
+    return fail(LTRK_EINVAL, "unknown wake model %d", w->model);
+  if (w->n_slices < 1 || w->n_slices > kWakeMaxSlices)
+    return fail(LTRK_EINVAL, "n_slices must be in [1, %d]", kWakeMaxSlices);
+  if (!(w->z_hi > w->z_lo)) return fail(LTRK_EINVAL, "z_hi must be > z_lo");
+  if (!(w->intensity >= 0.0)) return fail(LTRK_EINVAL, "intensity must be >= 0");
+  if (w->model == LTRK_WAKE_RESONATOR && (!(w->freq_hz > 0.0) || !(w->quality > 0.5)))
+    return fail(LTRK_EINVAL, "resonator needs freq_hz > 0 and quality > 1/2");
+  return LTRK_OK;
+}
+
+// Blocks of the wake turn kernel (grid-stride over wave tiles): each adds its
+// slice histogram into the global counts once per turn, so fewer blocks mean
+// fewer contended adds and more tiles per block. LTRK_WAKE_BLOCKS overrides
+// the default (1 .. kWakeMaxBlocks).
+int wake_blocks() {
+  static const int blocks = [] {
+    const char* e = std::getenv("LTRK_WAKE_BLOCKS");
+    const long v = e ? std::atol(e) : kWakeMaxBlocks;
+    return static_cast<int>(std::min<long>(std::max<long>(v, 1), kWakeMaxBlocks));
+  }();
+  return blocks;
+}
+
+// W at tau = m dz / (beta c), m < n_slices (W(0): half the limit).
+void make_wake_table(const ltrk_wake& w, double beta, double* tab) {
+  const double c_light = 299792458.0;
+  const double dz = (w.z_hi - w.z_lo) / static_cast<double>(w.n_slices);
+  const double tau1 = dz / (beta * c_light);
+  if (w.model == LTRK_WAKE_CONSTANT) {
+    for (int m = 0; m < w.n_slices; ++m) tab[m] = m == 0 ? 0.5 * w.shunt : w.shunt;
+    return;
+  }
+  const double omega_r = 2.0 * M_PI * w.freq_hz;
+  const double alpha = omega_r / (2.0 * w.quality);
+  const double omega_bar = std::sqrt(omega_r * omega_r - alpha * alpha);
+  tab[0] = alpha * w.shunt;
+  for (int m = 1; m < w.n_slices; ++m) {
+    const double tau = static_cast<double>(m) * tau1;
+    tab[m] = 2.0 * alpha * w.shunt * std::exp(-alpha * tau) *
+             (std::cos(omega_bar * tau) - alpha / omega_bar * std::sin(omega_bar * tau));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 6-D map: Twiss parameters of the transverse planes
 
 int validate_twiss(const ltrk_twiss* t) {
@@ -440,8 +492,9 @@ struct Scratch {
   size_t bytes = 0;
 };
 
-// Per-stream programme records: device copy, pinned staging, and an event
-// recorded after the last copy out of the staging buffer.
+// Per-stream staged tables (programme records, wake table): device copy,
+// pinned staging, and an event recorded after the last copy out of the
+// staging buffer.
 struct ProgBuf {
   void* dev = nullptr;
   size_t dev_bytes = 0;
@@ -684,7 +737,8 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   }
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  const ltrk_plan plan = choose_plan(integrator, dtype, n, false);
+  ltrk_plan plan = choose_plan(integrator, dtype, n, false);
+  if (ext) plan.ppl = std::max(plan.ppl, 4);  // extended kernels: 4 or 8 particles per lane
 
   BunchDev b;
   std::memset(&b, 0, sizeof(b));
@@ -811,8 +865,8 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
   ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false);
-  // six FP64 coordinates per particle: at most 4 particles per lane
-  const int ppl = std::min(plan.ppl, 4);
+  // six FP64 coordinates per particle: 4 particles per lane
+  constexpr int ppl = 4;
 
   Bunch6Dev b;
   std::memset(&b, 0, sizeof(b));
@@ -866,7 +920,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
       bl.partials = static_cast<double*>(scratch);
       const int32_t row0 = static_cast<int32_t>(j);
       const int block = plan.block;
-      seq.push_back({kTimeTrack, [bl, c6, row0, ppl, block](hipStream_t st) {
+      seq.push_back({kTimeTrack, [bl, c6, row0, block](hipStream_t st) {
                        return launch_track_6d(bl, c6, row0, ppl, block, st);
                      }});
     }
@@ -887,6 +941,138 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
       }
     }
   }
+  return execute(c, key, seq, s, plan.use_graph != 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tracking with a wake kick after every turn
+
+static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                      const ltrk_wake* wk, int integrator, ltrk_moments* mom, hipStream_t s) {
+  int rc = validate_rf2(rf);
+  if (rc) return rc;
+  if ((rc = validate_wake(wk))) return rc;
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
+  if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
+  if (turns >= INT32_MAX) return fail(LTRK_EINVAL, "turns must be < 2^31 - 1");
+  if (turns == 0) return LTRK_OK;
+  if (stream_capturing(s))
+    return fail(LTRK_EUNSUPPORTED, "the wake table upload cannot be captured into a graph");
+  if (mom && (rc = check_device_range(mom, static_cast<size_t>(turns) * sizeof(ltrk_moments),
+                                      "moments")))
+    return rc;
+  if (n == 0) {
+    if (!mom) return LTRK_OK;
+    hipError_t e = launch_fill_nan(mom, turns, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "fill moments");
+  }
+  const size_t bytes = static_cast<size_t>(n) * sizeof(double);
+  if ((rc = check_device_range(z, bytes, "z"))) return rc;
+  if ((rc = check_device_range(dp, bytes, "dp"))) return rc;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false);
+  const int ppl = std::max(plan.ppl, 4);
+  const int block = plan.block;
+  const int wpb = block / kWave;
+
+  BunchDev b;
+  std::memset(&b, 0, sizeof(b));
+  b.z = z;
+  b.dp = dp;
+  b.n = n;
+  b.waves = waves_for(n, ppl);
+  b.integrator = integrator;
+  b.dtype = LTRK_F64;
+  b.active = 1;
+  CoeffsRf2 ce;
+  make_coeffs_rf2(*rf, integrator, &ce);
+  ltrk_derived d;
+  derive(rf->ring, &d);
+
+  const int grid = static_cast<int>(std::min<int64_t>((b.waves + wpb - 1) / wpb, wake_blocks()));
+  const int64_t gwaves = static_cast<int64_t>(grid) * wpb;  // moment columns
+  const int ns = wk->n_slices;
+  const int64_t groups = finalize_groups(gwaves);
+  const int64_t cols = scratch_cols(gwaves);
+
+  DeviceCtx& c = ctx_for(dev);
+  std::lock_guard<std::mutex> lock(c.mu);
+  int64_t rows = turns;
+  if (mom) {
+    rows = chunk_rows(turns, 1, cols, groups > 1);
+    if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)gwaves);
+  }
+  const size_t part_bytes = mom ? static_cast<size_t>(rows) * 5 * cols * sizeof(double) : 0;
+  const size_t hist_bytes = (static_cast<size_t>(ns) * sizeof(uint32_t) + 255) & ~size_t(255);
+  const size_t pot_bytes = static_cast<size_t>(ns) * sizeof(double);
+  void* scratch = nullptr;
+  if ((rc = ensure_scratch(c, s, part_bytes + hist_bytes + pot_bytes, &scratch))) return rc;
+  char* base = static_cast<char*>(scratch);
+
+  double* host = nullptr;
+  void* wtab = nullptr;
+  if ((rc = stage_program(c, s, pot_bytes, &host, &wtab))) return rc;
+  make_wake_table(*wk, d.beta, host);
+  if ((rc = send_program(c, s, pot_bytes))) return rc;
+
+  const double e_charge = 1.602176634e-19;
+  const double q_mp = rf->ring.charge_e * e_charge * wk->intensity / static_cast<double>(n);
+  WakeDev w;
+  std::memset(&w, 0, sizeof(w));
+  w.z_lo = wk->z_lo;
+  w.dz = (wk->z_hi - wk->z_lo) / static_cast<double>(ns);
+  w.kappa = rf->ring.charge_e * q_mp / (d.beta * rf->ring.p0c_eV);
+  w.wtab = static_cast<const double*>(wtab);
+  w.counts = reinterpret_cast<uint32_t*>(base + part_bytes);
+  w.pot = reinterpret_cast<double*>(base + part_bytes + hist_bytes);
+  w.n_slices = ns;
+  b.partials = mom ? reinterpret_cast<double*>(base) : nullptr;
+
+  std::string key;
+  key_add(key, 7);
+  key_add(key, b);
+  key_add(key, ce);
+  key_add(key, w);
+  key_add(key, plan);
+  key_add(key, ppl);
+  key_add(key, turns);
+  key_add(key, mom);
+
+  // A(t) kicks with turn t-1's potential and writes moment row t-1; row r
+  // lives at r - c0 in the chunk [c0, c0 + rows) finalized once complete.
+  std::vector<Launch> seq;
+  auto turn_launch = [&](int phase, int64_t row) {
+    const int32_t local = static_cast<int32_t>(row < 0 ? 0 : row % rows);
+    seq.push_back({kTimeTrack, [b, ce, w, phase, local, block, grid, ppl](hipStream_t st) {
+                     return launch_wake_turn(b, ce, w, phase, local, ppl, block, grid, st);
+                   }});
+    if (mom && row >= 0 && (row % rows == rows - 1 || row == turns - 1)) {
+      const int64_t c0 = row - row % rows;
+      FinalizeDev f;
+      std::memset(&f, 0, sizeof(f));
+      f.partials = b.partials;
+      f.stage = b.partials + rows * 5 * gwaves;
+      f.waves = gwaves;
+      f.groups = groups;
+      f.n = n;
+      f.out = mom + c0;
+      f.rows = static_cast<int32_t>(row - c0 + 1);
+      seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+    }
+  };
+  auto potential = [&]() {
+    seq.push_back({kTimeFinalize, [w](hipStream_t st) { return launch_wake_potential(w, st); }});
+  };
+  seq.push_back({kTimeFinalize, [w](hipStream_t st) { return launch_wake_zero(w, st); }});
+  turn_launch(0, -1);
+  for (int64_t t = 1; t < turns; ++t) {
+    potential();
+    turn_launch(1, t - 1);
+  }
+  potential();
+  turn_launch(2, turns - 1);
   return execute(c, key, seq, s, plan.use_graph != 0);
 }
 
@@ -1279,6 +1465,15 @@ int ltrk_track_6d_f64(double* z, double* dp, double* x, double* xp, double* y, d
     arr[5] = yp;
     return track_6d(arr, n, turns, rf, twiss, integrator, moments,
                     static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_track_wake_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_rf2* rf,
+                        const ltrk_wake* wake, int integrator, ltrk_moments* moments,
+                        void* stream) {
+  LTRK_GUARD({
+    return track_wake(z, dp, n, turns, rf, wake, integrator, moments,
+                      static_cast<hipStream_t>(stream));
   })
 }
 

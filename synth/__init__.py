@@ -34,6 +34,11 @@ SPS_DOUBLE_RF = dict(SPS_RING, phi1_rad=0.0, harmonic2=9240.0, voltage2_V=0.5e6,
 SPS_TWISS = dict(q_x=20.13, qp_x=1.5, alpha_x=0.7, beta_x=42.0,
                  q_y=20.18, qp_y=-2.5, alpha_y=-1.1, beta_y=87.0)
 
+# Longitudinal wake of the wake workload: a broadband resonator (10 kOhm,
+# 1 GHz, Q = 1) on a bunch of 1e11 protons, 256 slices over +-0.8 m.
+SPS_WAKE = dict(model="resonator", n_slices=256, shunt=1e4, freq_hz=1.0e9, quality=1.0,
+                intensity=1e11, z_lo=-0.8, z_hi=0.8)
+
 SIGMA_Z = 0.23      # metres
 SIGMA_DP = 1.0e-3   # relative momentum deviation
 

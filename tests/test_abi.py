@@ -205,3 +205,29 @@ def test_6d_validation_before_any_launch():
     assert f(*nul, 0, 0, ctypes.byref(rf), None, 1, None, None) == ltrk.LTRK_EINVAL
     assert f(*nul, 10, 5, ctypes.byref(rf), ctypes.byref(ltrk.Twiss.of(tw)), 1, None,
              None) == ltrk.LTRK_EINVAL  # NULL state arrays
+
+
+def test_wake_validation_before_any_launch():
+    lib = _raw()
+    f = lib.ltrk_track_wake_f64
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.POINTER(ltrk.Rf2), ctypes.POINTER(ltrk.Wake), ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    rf = ltrk.Rf2.of(dict(SPS_RING, phi1_rad=0.0, harmonic2=9240.0, voltage2_V=0.0,
+                          phi2_rad=0.0, eta1=0.0, eta2=0.0))
+    good = dict(model="resonator", n_slices=64, shunt=1e4, freq_hz=1e9, quality=1.0,
+                intensity=1e11, z_lo=-1.0, z_hi=1.0)
+    assert f(None, None, 0, 0, ctypes.byref(rf), ctypes.byref(ltrk.Wake.of(good)), 1, None,
+             None) == 0
+    for key, val in [("n_slices", 0), ("n_slices", 4097), ("quality", 0.5), ("freq_hz", 0.0),
+                     ("z_hi", -1.0), ("intensity", -1.0), ("model", 2),
+                     ("shunt", float("nan"))]:
+        bad = ltrk.Wake.of(dict(good, **{key: val}))
+        assert f(None, None, 0, 0, ctypes.byref(rf), ctypes.byref(bad), 1, None,
+                 None) == ltrk.LTRK_EINVAL, key
+    # a constant wake needs no frequency or quality
+    const = ltrk.Wake.of(dict(good, model="constant", freq_hz=0.0, quality=0.0))
+    assert f(None, None, 0, 0, ctypes.byref(rf), ctypes.byref(const), 1, None, None) == 0
+    assert f(None, None, 0, 0, ctypes.byref(rf), None, 1, None, None) == ltrk.LTRK_EINVAL
+    assert f(None, None, 10, 5, ctypes.byref(rf), ctypes.byref(ltrk.Wake.of(good)), 1, None,
+             None) == ltrk.LTRK_EINVAL  # NULL state arrays
