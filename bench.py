@@ -110,24 +110,39 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
-    """The FP64 oracle on the host cores: a bounded sample of the workload
-    (the same bunch, its first T turns), scaled to particle-turns/s."""
+def _oracle_rate(z0, dp0, turns_total, ring, threads, budget_s):
+    """Oracle particle-turns/s on `threads` threads over the first turns of the
+    workload that fit in about budget_s seconds; returns (rate, turns, seconds)."""
     import oracle
-    from synth import SIGMA_DP, SIGMA_Z, gaussian_bunch
-    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
-    threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    z, dp, _ = oracle.track(z0, dp0, 2, ring, "leapfrog", threads=threads)
+    oracle.track(z0, dp0, 2, ring, "leapfrog", threads=threads)
     per_turn = (time.perf_counter() - t0) / 2
     turns = int(max(2, min(turns_total, budget_s / max(per_turn, 1e-9))))
     t0 = time.perf_counter()
     oracle.track(z0, dp0, turns, ring, "leapfrog", threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n * turns / dt, "unit": "particle-turns/s", "cores": threads,
-            "kind": "oracle",
+    return z0.size * turns / dt, turns, dt
+
+
+def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
+    """The FP64 oracle on the host cores: a bounded sample of the workload
+    (the same bunch, its first T turns), scaled to particle-turns/s; also on
+    one core (a tenth of the bunch, a third of the budget)."""
+    import platform
+    from synth import SIGMA_DP, SIGMA_Z, gaussian_bunch
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
+    threads = len(os.sched_getaffinity(0))
+    rate, turns, dt = _oracle_rate(z0, dp0, turns_total, ring, threads, budget_s)
+    n1 = max(1, n // 10)
+    rate1, turns1, dt1 = _oracle_rate(z0[:n1], dp0[:n1], turns_total, ring, 1, budget_s / 3)
+    return {"value": rate, "unit": "particle-turns/s", "cores": threads, "kind": "oracle",
             "sample": "%d particles x first %d of %d turns, leap-frog FP64 with moments every "
-                      "turn, OpenMP over particles, %.1f s wall" % (n, turns, turns_total, dt)}
+                      "turn, OpenMP over particles, %.1f s wall" % (n, turns, turns_total, dt),
+            "ns_per_particle_turn": 1e9 / rate,
+            "single_core": {"value": rate1, "ns_per_particle_turn": 1e9 / rate1,
+                            "sample": "%d particles x first %d turns on 1 thread, %.1f s wall"
+                                      % (n1, turns1, dt1)},
+            "host_cpu": platform.processor() or platform.machine()}
 
 
 def bench_default(args):
@@ -253,9 +268,12 @@ def bench_default(args):
     out.update(extras)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(n, T, SPS_RING, seed, budget_s=args.cpu_seconds)
-        log("cpu: %.4e particle-turns/s on %d threads" % (out["cpu_baseline"]["value"],
-                                                           out["cpu_baseline"]["cores"]))
+        cb = cpu_baseline(n, T, SPS_RING, seed, budget_s=args.cpu_seconds)
+        cb["gpu_speedup"] = {"all_cores": out["value"] / cb["value"],
+                             "single_core": out["value"] / cb["single_core"]["value"]}
+        out["cpu_baseline"] = cb
+        log("cpu: %.4e particle-turns/s on %d threads, %.4e on one" % (
+            cb["value"], cb["cores"], cb["single_core"]["value"]))
     print(json.dumps(out), flush=True)
 
 
@@ -667,6 +685,131 @@ def bench_wake(args):
                       "rows": rows}), flush=True)
 
 
+def _event_seconds(torch, stream, call):
+    """Device time of call() from events recorded on `stream` around it."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    call()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3
+
+
+def _latency_row(label, work, times):
+    t = np.asarray(times)
+    return {"config": label, "repeats": int(t.size), "p50_ms": float(np.percentile(t, 50)) * 1e3,
+            "p99_ms": float(np.percentile(t, 99)) * 1e3, "min_ms": float(t.min()) * 1e3,
+            "max_ms": float(t.max()) * 1e3,
+            "particle_turns_per_s_at_p50": work / float(np.percentile(t, 50))}
+
+
+def bench_latency(args):
+    """Whole-run latency percentiles, device time from events around each call
+    (every launch and the moment finalize included), inputs restored from
+    device-resident copies between repeats (outside the timed region):
+    config 1 (1000 x 1e3, leap-frog FP64, 50 repeats), config 3 (1e7 x 1e5,
+    leap-frog FP64 and F32C, 5 repeats) and config 4 (256 uneven bunches x 1e4
+    turns, FP64 and F32C, 5 repeats). With 5 repeats p99 is the maximum."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import (SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, batched_specs, gaussian_bunch,
+                       ring_for, split_f32c)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+
+    def single(label, n, T, seed, dtype, repeats):
+        z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
+        if dtype == "f64":
+            master = [torch.as_tensor(a).to(dev) for a in (z0, dp0)]
+        else:
+            zh, zc = split_f32c(z0)
+            dh, dc = split_f32c(dp0)
+            master = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+        work = [torch.empty_like(m) for m in master]
+        mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+        fn = ltrk.ltrk_track_f64 if dtype == "f64" else ltrk.ltrk_track_f32c
+        times = []
+        with torch.cuda.stream(stream):
+            for r in range(repeats + 1):  # the first call warms up
+                for w, m in zip(work, master):
+                    w.copy_(m)
+                t = _event_seconds(torch, stream, lambda: fn(*work, T, SPS_RING, "leapfrog", mom,
+                                                               stream=stream))
+                if r:
+                    times.append(t)
+        row = _latency_row(label, n * T, times)
+        rows.append(row)
+        log(json.dumps(row))
+
+    single("1: 1000 x 1e3, leap-frog FP64", 1000, 1000, SEEDS["small"], "f64", 50)
+    single("3: 1e7 x 1e5, leap-frog FP64", 10_000_000, 100_000, SEEDS["precision"], "f64", 5)
+    single("3: 1e7 x 1e5, leap-frog F32C", 10_000_000, 100_000, SEEDS["precision"], "f32c", 5)
+    T = 10_000
+    specs = batched_specs()
+    total = sum(sp.n for sp in specs)
+    for dtype in ("f64", "f32c"):
+        bunches, masters = [], []
+        for sp in specs:
+            r = ring_for(sp)
+            z0, dp0 = gaussian_bunch(sp.n, _matched_sigma_z(ltrk, r, sp.sigma_dp), sp.sigma_dp,
+                                     sp.seed)
+            if dtype == "f64":
+                m = [torch.as_tensor(a).to(dev) for a in (z0, dp0)]
+                keys = ("z", "dp")
+            else:
+                zh, zc = split_f32c(z0)
+                dh, dc = split_f32c(dp0)
+                m = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+                keys = ("z", "dp", "z_comp", "dp_comp")
+            b = {"ring": r, "moments": torch.empty((T, 5), dtype=torch.float64, device=dev)}
+            for k, a in zip(keys, m):
+                b[k] = torch.empty_like(a)
+            bunches.append(b)
+            masters.append(list(zip(keys, m)))
+        times = []
+        with torch.cuda.stream(stream):
+            for rep in range(6):
+                for b, m in zip(bunches, masters):
+                    for k, a in m:
+                        b[k].copy_(a)
+                t = _event_seconds(torch, stream, lambda: ltrk.ltrk_track_batched(
+                    bunches, T, "leapfrog", dtype, stream=stream))
+                if rep:
+                    times.append(t)
+        row = _latency_row("4: 256 bunches (%d particles) x 1e4, leap-frog %s" % (total, dtype.upper()),
+                           total * T, times)
+        rows.append(row)
+        log(json.dumps(row))
+        del bunches, masters
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "latency percentiles, configs 1, 3, 4", "rows": rows}),
+          flush=True)
+
+
+def bench_counters_f32c(args):
+    """The fused F32C leap-frog kernel at 1e6 particles in the benchmark's plan
+    (4 launches), for FP32 / FP64 VALU counter passes."""
+    import torch
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch, split_f32c
+    dev = torch.device("cuda:0")
+    n = 1_000_000
+    z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+    zh, zc = split_f32c(z0)
+    dh, dc = split_f32c(dp0)
+    arrs = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+    plan = ltrk.ltrk_get_plan("leapfrog", "f32c", n)
+    K = plan["turns_per_launch"]
+    ltrk.ltrk_set_plan(K, plan["block"], plan["ppl"], 0)
+    mom = torch.empty((4 * K, 5), dtype=torch.float64, device=dev)
+    ltrk.ltrk_track_f32c(*arrs, 4 * K, SPS_RING, "leapfrog", mom)
+    torch.cuda.synchronize()
+    ltrk.ltrk_set_plan()
+    print(json.dumps({"workload": "counters_f32c", "plan": plan}), flush=True)
+
+
 def _matched_sigma_z(ltrk, ring, sigma_dp):
     d = ltrk.ltrk_derive(ring)
     return sigma_dp * d["slip_length"] / d["omega_s"]
@@ -872,7 +1015,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
-                             "counters", "schemes", "rf2", "program", "6d", "wake"])
+                             "counters", "counters_f32c", "schemes", "rf2", "program", "6d",
+                             "wake", "latency"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
@@ -899,7 +1043,8 @@ def main():
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
      "counters": bench_counters, "schemes": bench_schemes,
-     "rf2": bench_rf2, "program": bench_program, "6d": bench_6d, "wake": bench_wake}[args.workload](args)
+     "rf2": bench_rf2, "program": bench_program, "6d": bench_6d, "wake": bench_wake,
+     "latency": bench_latency, "counters_f32c": bench_counters_f32c}[args.workload](args)
 
 
 if __name__ == "__main__":
