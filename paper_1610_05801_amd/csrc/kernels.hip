@@ -28,12 +28,15 @@
 //     are bit-identical for any K, block size or batching with the same P.
 //
 // The RF kick evaluates sin(k z) as sin(pi u), u = (2h/C) z in half
-// revolutions: n = rint(u), r = u - n is exact (Sterbenz) and |r| <= 1/2, the
-// polynomial of gen_sinpi.py (with the kick weight folded into its
-// coefficients on the host) gives the scaled sin(pi r), and (-1)^n restores
-// the sign.
-// The reduction is branch-free and exact for any z, so particles that left
-// the bucket (large z) cost the same as the core.
+// revolutions: n = rint(u), r = u - n with |r| <= 1/2, the polynomial of
+// gen_sinpi.py (with the kick weight folded into its coefficients on the
+// host) gives the scaled sin(pi r), and (-1)^n restores the sign. A wave
+// whose positions stay below 2^50 C/(2h) in magnitude for the whole launch
+// (in_exact_range, checked once after the load) reduces the product (2h/C) z
+// without rounding it first, two FMAs giving n and r (exact_product); other
+// waves round u first and reduce it exactly for any finite z. Both are
+// branch-free, so particles that left the bucket (large z) cost the same as
+// the core.
 //
 // All arithmetic is written with explicit fma(); the library is compiled with
 // -ffp-contract=off so the rounding of every operation is fixed by the source.
@@ -41,6 +44,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "kernels.h"
 #include "ltrk_device.h"
@@ -61,32 +66,32 @@ __device__ __forceinline__ void kahan_add(float& x, float& c, float inc) {
 // ---------------------------------------------------------------------------
 // One turn, FP64 state
 
-template <int INTEG>
+template <int INTEG, bool EXACT>
 __device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) {
   const double s = c.half_rev_per_m;
   if constexpr (INTEG == kEulerCromer) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = kicked(d, z * s, c.kq[0]);
+    d = kicked<EXACT>(d, z, s, c.kq[0]);
   } else if constexpr (INTEG == kLeapfrog) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = kicked(d, z * s, c.kq[0]);
+    d = kicked<EXACT>(d, z, s, c.kq[0]);
     z = __builtin_fma(c.nd[0], d, z);
   } else if constexpr (INTEG == kRuth4) {
     z = __builtin_fma(c.nd[0], d, z);
-    d = kicked(d, z * s, c.kq[0]);
+    d = kicked<EXACT>(d, z, s, c.kq[0]);
     z = __builtin_fma(c.nd[1], d, z);
-    d = kicked(d, z * s, c.kq[1]);
+    d = kicked<EXACT>(d, z, s, c.kq[1]);
     z = __builtin_fma(c.nd[1], d, z);
-    d = kicked(d, z * s, c.kq[0]);
+    d = kicked<EXACT>(d, z, s, c.kq[0]);
     z = __builtin_fma(c.nd[0], d, z);
   } else if constexpr (INTEG == kRk4) {
-    const double k1z = c.neg_D * d, k1d = scaled_sin(z * s, c.kq[0]);
+    const double k1z = c.neg_D * d, k1d = scaled_sin<EXACT>(z, s, c.kq[0]);
     const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
-    const double k2z = c.neg_D * d2, k2d = scaled_sin(z2 * s, c.kq[0]);
+    const double k2z = c.neg_D * d2, k2d = scaled_sin<EXACT>(z2, s, c.kq[0]);
     const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
-    const double k3z = c.neg_D * d3, k3d = scaled_sin(z3 * s, c.kq[0]);
+    const double k3z = c.neg_D * d3, k3d = scaled_sin<EXACT>(z3, s, c.kq[0]);
     const double z4 = z + k3z, d4 = d + k3d;
-    const double k4z = c.neg_D * d4, k4d = scaled_sin(z4 * s, c.kq[0]);
+    const double k4z = c.neg_D * d4, k4d = scaled_sin<EXACT>(z4, s, c.kq[0]);
     z = __builtin_fma(1.0 / 6.0, (k1z + 2.0 * k2z) + (2.0 * k3z + k4z), z);
     d = __builtin_fma(1.0 / 6.0, (k1d + 2.0 * k2d) + (2.0 * k3d + k4d), d);
   }
@@ -100,7 +105,7 @@ __device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) 
 // hi - comp, sin in FP64) rounded once to FP32. RK4 evaluates its stages in
 // FP64 from the FP64 state value and adds FP32-rounded increments.
 
-template <int INTEG>
+template <int INTEG, bool EXACT>
 __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float& dc,
                                           const Coeffs& c) {
   const double s = c.half_rev_per_m;
@@ -110,7 +115,7 @@ __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float
   };
   auto kick = [&](const double* q) {
     const double zv = static_cast<double>(zh) - static_cast<double>(zc);
-    kahan_add(dh, dc, static_cast<float>(scaled_sin(zv * s, q)));
+    kahan_add(dh, dc, static_cast<float>(scaled_sin<EXACT>(zv, s, q)));
   };
   if constexpr (INTEG == kEulerCromer) {
     drift(c.nd_f[0]);
@@ -130,25 +135,26 @@ __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float
   } else if constexpr (INTEG == kRk4) {
     const double z = static_cast<double>(zh) - static_cast<double>(zc);
     const double d = static_cast<double>(dh) - static_cast<double>(dc);
-    const double k1z = c.neg_D * d, k1d = scaled_sin(z * s, c.kq[0]);
+    const double k1z = c.neg_D * d, k1d = scaled_sin<EXACT>(z, s, c.kq[0]);
     const double z2 = __builtin_fma(0.5, k1z, z), d2 = __builtin_fma(0.5, k1d, d);
-    const double k2z = c.neg_D * d2, k2d = scaled_sin(z2 * s, c.kq[0]);
+    const double k2z = c.neg_D * d2, k2d = scaled_sin<EXACT>(z2, s, c.kq[0]);
     const double z3 = __builtin_fma(0.5, k2z, z), d3 = __builtin_fma(0.5, k2d, d);
-    const double k3z = c.neg_D * d3, k3d = scaled_sin(z3 * s, c.kq[0]);
+    const double k3z = c.neg_D * d3, k3d = scaled_sin<EXACT>(z3, s, c.kq[0]);
     const double z4 = z + k3z, d4 = d + k3d;
-    const double k4z = c.neg_D * d4, k4d = scaled_sin(z4 * s, c.kq[0]);
+    const double k4z = c.neg_D * d4, k4d = scaled_sin<EXACT>(z4, s, c.kq[0]);
     kahan_add(zh, zc, static_cast<float>((1.0 / 6.0) * ((k1z + 2.0 * k2z) + (2.0 * k3z + k4z))));
     kahan_add(dh, dc, static_cast<float>((1.0 / 6.0) * ((k1d + 2.0 * k2d) + (2.0 * k3d + k4d))));
   }
 }
 
-// Turn functor of the single-harmonic map for wave_f64.
-template <int INTEG>
+// Turn functor of the single-harmonic map for wave_f64 (EXACT: the
+// exact-product phase reduction).
+template <int INTEG, bool EXACT>
 struct SingleRf {
   const Coeffs& c;
   __device__ __forceinline__ int at(int) const { return 0; }
   __device__ __forceinline__ void operator()(int, double& z, double& d) const {
-    turn_f64<INTEG>(z, d, c);
+    turn_f64<INTEG, EXACT>(z, d, c);
   }
 };
 
@@ -174,25 +180,44 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  for (int t = 0; t < turns; t += kFlushTurns) {
-    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
-    for (int j = 0; j < nb; ++j) {
-      Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+  auto loop = [&](auto exact) {
+    constexpr bool EXACT = decltype(exact)::value;
+    for (int t = 0; t < turns; t += kFlushTurns) {
+      const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
+      for (int j = 0; j < nb; ++j) {
+        Sums s;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        turn_f32c<INTEG>(zh[p], zc[p], dh[p], dc[p], b.c);
-        if constexpr (MOM)
-          accumulate(s, static_cast<double>(zh[p]) - static_cast<double>(zc[p]),
-                     static_cast<double>(dh[p]) - static_cast<double>(dc[p]));
+        for (int p = 0; p < P; ++p) {
+          turn_f32c<INTEG, EXACT>(zh[p], zc[p], dh[p], dc[p], b.c);
+          if constexpr (MOM) {
+            const double zv = static_cast<double>(zh[p]) - static_cast<double>(zc[p]);
+            const double dv = static_cast<double>(dh[p]) - static_cast<double>(dc[p]);
+            if (p == 0)
+              s = first_sums(zv, dv);
+            else
+              accumulate(s, zv, dv);
+          }
+        }
+        if constexpr (MOM) stage_sums(buf, j, s, lane);
       }
-      if constexpr (MOM) stage_sums(buf, j, s, lane);
+      if constexpr (MOM) {
+        wave_sync();
+        flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
+        wave_sync();
+      }
     }
-    if constexpr (MOM) {
-      wave_sync();
-      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
-      wave_sync();
-    }
+  };
+  // The phase is formed from hi - comp, within |hi| + |comp| of zero.
+  double za[P], da[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    za[p] = __builtin_fabs(static_cast<double>(zh[p])) + __builtin_fabs(static_cast<double>(zc[p]));
+    da[p] = __builtin_fabs(static_cast<double>(dh[p])) + __builtin_fabs(static_cast<double>(dc[p]));
   }
+  if (in_exact_range<P>(b.c, za, da, turns))
+    loop(std::true_type{});
+  else
+    loop(std::false_type{});
   if constexpr (INTEG != kMeasureOnly) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -211,11 +236,12 @@ template <int INTEG, int DT, int P>
 __device__ __forceinline__ void run_wave(const BunchDev& b, int64_t w, int turns, int row0,
                                          double* buf) {
   if constexpr (DT == kF64) {
-    const SingleRf<INTEG> turn{b.c};
+    const SingleRf<INTEG, true> exact{b.c};
+    const SingleRf<INTEG, false> safe{b.c};
     if (b.partials)
-      wave_f64<INTEG, P, true, false>(b, turn, w, turns, row0, buf);
+      wave_f64<INTEG, P, true, false>(b, exact, safe, w, turns, row0, buf);
     else
-      wave_f64<INTEG, P, false, false>(b, turn, w, turns, row0, buf);
+      wave_f64<INTEG, P, false, false>(b, exact, safe, w, turns, row0, buf);
   } else {
     if (b.partials)
       wave_f32c<INTEG, P, true>(b, w, turns, row0, buf);

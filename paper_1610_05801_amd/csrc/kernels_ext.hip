@@ -88,9 +88,9 @@ __device__ __forceinline__ void wave_ext(const BunchDev& b, const Turn& turn, in
     for (int j = 0; j < nb; ++j) {
       turn.template all<P, TAIL>(turn.at(t + j), z, d, live);
       if constexpr (MOM) {
-        Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+        Sums s = first_sums(z[0], d[0]);
 #pragma unroll
-        for (int p = 0; p < P; ++p) accumulate(s, z[p], d[p]);
+        for (int p = 1; p < P; ++p) accumulate(s, z[p], d[p]);
         stage_sums(buf, j, s, lane);
       }
     }
@@ -133,7 +133,8 @@ __device__ __forceinline__ void run_wave_ext(const BunchDev& b, const Turn& turn
 
 // sin(pi u) and cos(pi u) from one reduction: n = rint(u), r = u - n exact,
 // sin(pi r) = r g(r^2) and cos(pi r) = sin(pi t) = t g(t^2) with t = 1/2 - |r|,
-// both times (-1)^n.
+// both times (-1)^n (the parity from the last mantissa bit of |n| + 2^52, as
+// in kick_terms).
 __device__ __forceinline__ void sincos_pi(double u, double& s, double& c) {
   const double n = __builtin_rint(u);
   const double r = u - n;
@@ -146,9 +147,8 @@ __device__ __forceinline__ void sincos_pi(double u, double& s, double& c) {
     pc = __builtin_fma(pc, t2, kSinPiCoeff[j]);
   }
   const double m = __builtin_fabs(n) + 0x1p52;
-  const uint64_t odd = (__builtin_bit_cast(uint64_t, m) & 1ull) << 63;
-  s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r * ps) ^ odd);
-  c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, t * pc) ^ odd);
+  s = parity_signed(r * ps, m);
+  c = parity_signed(t * pc, m);
 }
 
 __device__ __forceinline__ void rotate(double& u, double& v, double d, const PlaneDev& p) {
@@ -196,9 +196,10 @@ __device__ __forceinline__ void wave_6d(const Bunch6Dev& b, const Coeffs6d& c, i
       }
       turn_ext<INTEG, false, H, P, TAIL>(s6[0], s6[1], live, c.rf, src);
       if constexpr (MOM) {
-        Sums sl{0.0, 0.0, 0.0, 0.0, 0.0}, sx{0.0, 0.0, 0.0, 0.0, 0.0}, sy{0.0, 0.0, 0.0, 0.0, 0.0};
+        Sums sl = first_sums(s6[0][0], s6[1][0]), sx = first_sums(s6[2][0], s6[3][0]),
+             sy = first_sums(s6[4][0], s6[5][0]);
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
+        for (int p = 1; p < P; ++p) {
           accumulate(sl, s6[0][p], s6[1][p]);
           accumulate(sx, s6[2][p], s6[3][p]);
           accumulate(sy, s6[4][p], s6[5][p]);

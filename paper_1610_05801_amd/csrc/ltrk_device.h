@@ -39,6 +39,9 @@ struct Coeffs {
                                // delta += r * sum_j kq[j] r^2j (scheme specific; RK4: kq[0]
                                // carries A)
   double neg_D;                // -D (RK4 field)
+  double z_exact;              // 2^50 / s: the exact-product phase reduction holds for |z| below
+  double reach_d, reach_k;     // per-turn bounds: |dz| <= reach_d (|delta| + reach_k),
+                               // |d delta| <= reach_k (in_exact_range)
   float nd_f[2][2];            // nd split into FP32 hi + lo (F32C drift increments:
                                // fma(hi, v, lo * v) carries the coefficient to ~2^-48)
 };

@@ -108,6 +108,7 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
   c->half_rev_per_m = 2.0 * r.harmonic / r.circumference_m;
   c->neg_D = -D;
   double kw[2] = {A, 0.0};  // kick weights x A
+  double drift_sum = 1.0, kick_sum = 1.0;  // summed absolute drift and kick weights
   switch (integrator) {
     case LTRK_EULER_CROMER:
       c->nd[0] = -D;
@@ -122,11 +123,17 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
       c->nd[1] = -((0.5 * (1.0 - th)) * D);
       kw[0] = th * A;
       kw[1] = (1.0 - 2.0 * th) * A;
+      drift_sum = th + (th - 1.0);
+      kick_sum = 2.0 * th + (2.0 * th - 1.0);
       break;
     }
-    default:  // RK4: the force A sin(k z)
+    default:  // RK4: the force A sin(k z); a step moves delta by at most |A| and
+              // z (stages included) by at most |D| (|delta| + |A|)
       break;
   }
+  c->z_exact = 0x1p50 / c->half_rev_per_m;
+  c->reach_d = drift_sum * std::fabs(D);
+  c->reach_k = kick_sum * std::fabs(A);
   static_assert(kSinTerms == kSinPiTerms, "polynomial length");
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < kSinTerms; ++j) c->kq[i][j] = kw[i] * kSinPiCoeff[j];

@@ -14,37 +14,111 @@ namespace ltrk {
 // ---------------------------------------------------------------------------
 // Elementary operations
 
-// Kick terms for phase u (in half revolutions): returns r' and p with
-// r' * p = (scale) * sin(pi u), where q holds scale * kSinPiCoeff. n = rint(u),
-// r = u - n is exact (|r| <= 1/2), p = sum_j q[j] r^2j, and the sign (-1)^n is
-// applied to r: for |n| < 2^52 the parity of n is the last mantissa bit of
-// |n| + 2^52; larger |u| has r = 0, where the sign is moot.
+// Kick terms: r' and p with r' * p = (scale) * sin(pi u) for a phase u in
+// half revolutions, where q holds scale * kSinPiCoeff. n = rint(u), r = u - n
+// (|r| <= 1/2), p = sum_j q[j] r^2j, and the sign (-1)^n is applied to r.
+// Two reductions:
+//   - kick_terms(u): u is a double; r = u - n is exact (Sterbenz). For
+//     |n| < 2^52 the parity of n is the last mantissa bit of |n| + 2^52;
+//     larger |u| are integers, r = 0 and the sign is moot. Exact for every
+//     finite u.
+//   - kick_terms_at(z, s): u = s z is never rounded on its own. t = s z +
+//     1.5 * 2^52 in one FMA lands in [2^52, 2^53) for |s z| < 2^51, where
+//     the doubles are the integers, so t = 1.5 * 2^52 + rint(s z) (ties to
+//     even, 1.5 * 2^52 being even) and its last mantissa bit is the parity;
+//     n = t - 1.5 * 2^52 is exact and r = s z - n takes a second FMA with one
+//     rounding. Two instructions fewer than forming u first. Outside
+//     |s z| < 2^51 r is unbounded, so callers use it only for waves whose
+//     positions in_exact_range() has bounded for the whole launch.
+constexpr double kRoundMagic = 0x1.8p52;
+constexpr double kExactRange = 0x1p50;  // |s z| bound of the exact-product reduction, 2x margin
+
 struct KickTerms {
   double r, p;
 };
 
-__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
-  const double n = __builtin_rint(u);
-  const double r = u - n;
+// r with its sign flipped when the last mantissa bit of t is set: that bit
+// moved to bit 31 of r's high word and added there flips the sign (the carry
+// out of the word is dropped). Written as one v_lshl_add_u32: from plain C++
+// the compiler widens the add to 64 bits and spends four or five
+// instructions on it.
+struct Words {
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ double parity_signed(double r, double t) {
+  Words w = __builtin_bit_cast(Words, r);
+  const uint32_t tl = __builtin_bit_cast(Words, t).lo;
+  uint32_t hi;
+  asm("v_lshl_add_u32 %0, %1, 31, %2" : "=v"(hi) : "v"(tl), "v"(w.hi));
+  w.hi = hi;
+  return __builtin_bit_cast(double, w);
+}
+
+__device__ __forceinline__ KickTerms terms_of(double r, double t, const double* __restrict__ q) {
   const double s = r * r;
   double p = q[kSinTerms - 1];
 #pragma unroll
   for (int j = kSinTerms - 2; j >= 0; --j) p = __builtin_fma(p, s, q[j]);
-  const double t = __builtin_fabs(n) + 0x1p52;
-  const uint64_t odd = (__builtin_bit_cast(uint64_t, t) & 1ull) << 63;
-  return KickTerms{__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd), p};
+  return KickTerms{parity_signed(r, t), p};
 }
 
-// scale * sin(pi u) as one product.
-__device__ __forceinline__ double scaled_sin(double u, const double* __restrict__ q) {
-  const KickTerms k = kick_terms(u, q);
+__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
+  const double n = __builtin_rint(u);
+  return terms_of(u - n, __builtin_fabs(n) + 0x1p52, q);
+}
+
+__device__ __forceinline__ KickTerms kick_terms_at(double z, double s,
+                                                   const double* __restrict__ q) {
+  const double t = __builtin_fma(z, s, kRoundMagic);
+  const double n = t - kRoundMagic;
+  return terms_of(__builtin_fma(z, s, -n), t, q);
+}
+
+// Kick terms of the phase s z by either reduction.
+template <bool EXACT>
+__device__ __forceinline__ KickTerms kick_terms_sz(double z, double s,
+                                                   const double* __restrict__ q) {
+  if constexpr (EXACT)
+    return kick_terms_at(z, s, q);
+  else
+    return kick_terms(z * s, q);
+}
+
+// scale * sin(pi s z) as one product.
+template <bool EXACT>
+__device__ __forceinline__ double scaled_sin(double z, double s, const double* __restrict__ q) {
+  const KickTerms k = kick_terms_sz<EXACT>(z, s, q);
   return k.r * k.p;
 }
 
-// delta + scale * sin(pi u) with the last product fused into the update.
-__device__ __forceinline__ double kicked(double d, double u, const double* __restrict__ q) {
-  const KickTerms k = kick_terms(u, q);
+// delta + scale * sin(pi s z) with the last product fused into the update.
+template <bool EXACT>
+__device__ __forceinline__ double kicked(double d, double z, double s,
+                                        const double* __restrict__ q) {
+  const KickTerms k = kick_terms_sz<EXACT>(z, s, q);
   return __builtin_fma(k.r, k.p, d);
+}
+
+// Whether every position a wave reaches in a launch of `turns` turns keeps
+// |s z| < 2^50, so its turns may use the exact-product reduction. Per turn a
+// particle's momentum moves by at most reach_k and its position (also at the
+// intermediate stages of a turn) by at most reach_d * (|delta| + reach_k), so
+// after t < turns turns |z| <= |z0| + turns * reach_d * (|delta0| +
+// turns * reach_k) (host: reach_d = |D| and reach_k = |A| times the summed
+// absolute drift and kick weights of the scheme). Non-finite values fail the
+// test. The result is the same for every lane of the wave.
+template <int P>
+__device__ __forceinline__ bool in_exact_range(const Coeffs& c, const double (&z)[P],
+                                               const double (&d)[P], int turns) {
+  const double k = static_cast<double>(turns);
+  const double kd = k * c.reach_d;
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    ok = ok && __builtin_fma(kd, __builtin_fma(k, c.reach_k, __builtin_fabs(d[p])),
+                             __builtin_fabs(z[p])) < c.z_exact;
+  return __all(ok);
 }
 
 // Kahan-compensated x += inc with the running compensation c (value = x - c).
@@ -54,6 +128,12 @@ __device__ __forceinline__ double kicked(double d, double u, const double* __res
 struct Sums {
   double z, zz, d, dd, zd;
 };
+
+// The sums of a lane's first particle: what accumulate() into zero sums
+// gives (up to the sign of a zero), without the additions of zero.
+__device__ __forceinline__ Sums first_sums(double z, double d) {
+  return Sums{z, z * z, d, d * d, z * d};
+}
 
 __device__ __forceinline__ void accumulate(Sums& s, double z, double d) {
   s.z += z;
@@ -94,12 +174,16 @@ __device__ __forceinline__ void flush_rows(const double* buf, int rows, double* 
   double part_sum = 0.0;
   if (row < rows) {
     const double2* src = reinterpret_cast<const double2*>(buf + row * kRowStride + part * V);
+    // All LDS reads are issued before the first add (the scheduling barrier
+    // keeps the compiler from interleaving them in groups of four, each
+    // group waiting out the LDS latency: measured +3.5% on the fused kernel).
     double q[V / 2];
+    double2 v[V / 2];
 #pragma unroll
-    for (int j = 0; j < V / 2; ++j) {
-      const double2 v = src[j];
-      q[j] = v.x + v.y;
-    }
+    for (int j = 0; j < V / 2; ++j) v[j] = src[j];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < V / 2; ++j) q[j] = v[j].x + v[j].y;
 #pragma unroll
     for (int w = V / 4; w >= 1; w >>= 1) {
 #pragma unroll
@@ -122,6 +206,8 @@ __host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
 // ---------------------------------------------------------------------------
 // One wave tile for `turns` turns.
 
+// The turn loop of one wave tile over its P particles per lane, with the
+// per-turn moment sums staged in LDS rows and flushed every kFlushTurns turns.
 // A Turn functor gives per-turn data with at(t) (t counted from the launch's
 // first turn; nothing for maps with fixed coefficients) and applies one turn
 // with turn(data, z, d). TAIL marks the wave tile holding the end of the
@@ -130,8 +216,42 @@ __host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
 // kernels skip the check; maps with RF phase offsets or momentum steps move
 // it).
 template <int INTEG, int P, bool MOM, bool TAIL, class Turn>
-__device__ __forceinline__ void wave_f64(const BunchDev& b, const Turn& turn, int64_t w,
-                                         int turns, int row0, double* buf) {
+__device__ __forceinline__ void turn_loop(const Turn& turn, double (&z)[P], double (&d)[P],
+                                          const bool (&live)[P], int turns, double* buf,
+                                          double* out, int64_t waves, int lane) {
+  for (int t = 0; t < turns; t += kFlushTurns) {
+    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
+    for (int j = 0; j < nb; ++j) {
+      const auto tc = turn.at(t + j);
+      Sums s;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if constexpr (INTEG != kMeasureOnly) {
+          if (!TAIL || live[p]) turn(tc, z[p], d[p]);
+        }
+        if constexpr (MOM) {
+          if (p == 0)
+            s = first_sums(z[0], d[0]);
+          else
+            accumulate(s, z[p], d[p]);
+        }
+      }
+      if constexpr (MOM) stage_sums(buf, j, s, lane);
+    }
+    if constexpr (MOM) {
+      wave_sync();
+      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * waves, waves, lane);
+      wave_sync();
+    }
+  }
+}
+
+// One wave tile for `turns` turns: load, turn_loop, store. Exact is the turn
+// functor for waves that in_exact_range() admits, Safe the one for the rest
+// (the same type for maps with one reduction).
+template <int INTEG, int P, bool MOM, bool TAIL, class Exact, class Safe>
+__device__ __forceinline__ void wave_f64(const BunchDev& b, const Exact& exact, const Safe& safe,
+                                         int64_t w, int turns, int row0, double* buf) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t first = w * static_cast<int64_t>(kWave * P) + lane;
   double* __restrict__ zp = static_cast<double*>(b.z);
@@ -150,25 +270,13 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, const Turn& turn, in
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  for (int t = 0; t < turns; t += kFlushTurns) {
-    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
-    for (int j = 0; j < nb; ++j) {
-      const auto tc = turn.at(t + j);
-      Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        if constexpr (INTEG != kMeasureOnly) {
-          if (!TAIL || live[p]) turn(tc, z[p], d[p]);
-        }
-        if constexpr (MOM) accumulate(s, z[p], d[p]);
-      }
-      if constexpr (MOM) stage_sums(buf, j, s, lane);
-    }
-    if constexpr (MOM) {
-      wave_sync();
-      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
-      wave_sync();
-    }
+  if constexpr (INTEG == kMeasureOnly) {
+    turn_loop<INTEG, P, MOM, TAIL>(exact, z, d, live, turns, buf, out, b.waves, lane);
+  } else {
+    if (in_exact_range<P>(b.c, z, d, turns))
+      turn_loop<INTEG, P, MOM, TAIL>(exact, z, d, live, turns, buf, out, b.waves, lane);
+    else
+      turn_loop<INTEG, P, MOM, TAIL>(safe, z, d, live, turns, buf, out, b.waves, lane);
   }
   if constexpr (INTEG != kMeasureOnly) {
 #pragma unroll

@@ -7,6 +7,14 @@ and half-height dp_b, and
 Particles whose initial Hamiltonian lies within 1% of the separatrix value are
 "near-separatrix": there the map is chaotic and last-bit differences grow, so
 they get a looser bound and are counted separately.
+
+Two correct FP64 evaluations of the map round differently (the kernels'
+sine polynomial, fused multiply-adds and phase reduction against libm sin and
+separate roundings), so they differ by about one unit in the last place per
+turn; a particle's own orbit then amplifies that by the factor measured here
+(the oracle's response to a relative perturbation of 1e-13 of its initial z
+or delta). The per-particle bound is 8 ulp per turn times that factor
+(at least 1), the bound the extended-map tests use.
 """
 import numpy as np
 
@@ -42,3 +50,19 @@ def moment_error(m_gpu, m_ref):
         err[:, j] = np.abs(m_gpu[:, j] - m_ref[:, j]) / np.abs(m_ref[:, j])
     err[:, 4] = np.abs(m_gpu[:, 4] ** 2 - m_ref[:, 4] ** 2) / (m_ref[:, 1] * m_ref[:, 3]) ** 2
     return err
+
+
+def amplification(track, z0, dp0, turns, ring_like, integ, eps=1e-13, **kw):
+    """Oracle response, in the bucket norm, to perturbing z0 or dp0 by eps
+    (relative), divided by eps. `track` is the oracle function (track,
+    track_rf2, ...) called as track(z, dp, turns, ring_like, integ, **kw)."""
+    za, da = track(z0, dp0, turns, ring_like, integ, **kw)[:2]
+    zb, db = track(np.asarray(z0) * (1 + eps), dp0, turns, ring_like, integ, **kw)[:2]
+    zc, dc = track(z0, np.asarray(dp0) * (1 + eps), turns, ring_like, integ, **kw)[:2]
+    ring = ring_like
+    return np.maximum(bucket_error(zb, db, za, da, ring), bucket_error(zc, dc, za, da, ring)) / eps
+
+
+def rounding_tolerance(amp, turns):
+    """8 ulp (2^-53 each) per turn, amplified by the orbit (at least 1)."""
+    return 8 * 2.0 ** -53 * turns * np.maximum(amp, 1.0)

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 from synth import SPS_RING, gaussian_bunch
-from tests._parity import moment_error
+from tests._parity import amplification, moment_error, rounding_tolerance
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -87,7 +87,17 @@ def test_reduces_to_single_harmonic_kernel(ltrk):
     ms = torch.empty((500, 5), dtype=torch.float64, device="cuda")
     ltrk.ltrk_track_f64(zs, ds, 500, SPS_RING, "leapfrog", ms)
     torch.cuda.synchronize()
-    assert err(z, dp, zs.cpu().numpy(), ds.cpu().numpy()).max() <= 1e-13
+    # The two kernels reduce the RF phase differently (the single-harmonic one
+    # from the unrounded product s z, the extended one from u = fl(s z)), so
+    # they agree to rounding: 1e-13, or the rounding bound of a particle's
+    # own orbit where that is larger.
+    e = err(z, dp, zs.cpu().numpy(), ds.cpu().numpy())
+    tol = np.full_like(e, 1e-13)
+    over = e > tol
+    if np.any(over):
+        amp = amplification(oracle.track, z0[over], dp0[over], 500, SPS_RING, "leapfrog")
+        tol[over] = np.maximum(tol[over], rounding_tolerance(amp, 500))
+    assert np.all(e <= tol), (e.max(), over.sum())
     assert moment_error(mom, ms.cpu().numpy()).max() <= 1e-13
 
 
