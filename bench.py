@@ -2,11 +2,14 @@
 
 Default (the driver's contract): one step = tracking 1e6 particles for 1e4
 turns with FP64 leap-frog and moments after every turn (host constants, the
-fused turn kernels and the moment finalize: the whole hot path) on its own
-copy of a seeded Gaussian bunch already resident in HBM. Prints ONE JSON line
-on stdout; progress goes to stderr.
+fused turn kernels and the moment finalize: the whole hot path) of a seeded
+Gaussian bunch already resident in HBM, restored from a resident copy before
+each step outside the step's timer (each step is bracketed by device
+synchronisations; `value` is K steps of particle-turns over the sum of their
+times). Per-launch kernel times come from HIP events inside the replayed
+launch graph. Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 6]
 
 Other workloads (--workload): unfused (one launch per turn, HBM roofline
 sweep), precision (FP32+Kahan vs FP64, 1e7 particles), batched (256 uneven
@@ -162,29 +165,40 @@ def bench_default(args):
         plan = ltrk.ltrk_autotune(integ, "f64", n, stream=stream)
         log("autotuned plan", plan)
     plan = ltrk.ltrk_get_plan(integ, "f64", n)
-    nsteps = args.warmup + args.steps
-    # every step tracks its own copy of the initial bunch (inputs resident in HBM)
-    zs = [zt.to(dev) for _ in range(nsteps)]
-    ds = [dt.to(dev) for _ in range(nsteps)]
-    moms = [torch.empty((T, 5), dtype=torch.float64, device=dev) for _ in range(2)]
+    # Every step tracks the initial bunch from the same device buffers: before
+    # each step (outside its timer) the buffers are restored from a resident
+    # copy, so every step does the same work and replays the same cached
+    # graph. Timing is on from the first warm-up step, so the timed graph
+    # (per-launch event-record nodes) is built there and only replayed in the
+    # timed steps.
+    z_init, d_init = zt.to(dev), dt.to(dev)
+    z_run, d_run = torch.empty_like(z_init), torch.empty_like(d_init)
+    mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
+    moms = [mom]
     torch.cuda.synchronize()
 
-    with torch.cuda.stream(stream):
-        for i in range(args.warmup):
-            ltrk.ltrk_track_f64(zs[i], ds[i], T, SPS_RING, integ, moms[i % 2], stream=stream)
+    def restore():
+        z_run.copy_(z_init)
+        d_run.copy_(d_init)
         stream.synchronize()
+
+    with torch.cuda.stream(stream):
         ltrk.ltrk_timing_enable(True)
+        for i in range(args.warmup):
+            restore()
+            ltrk.ltrk_track_f64(z_run, d_run, T, SPS_RING, integ, mom, stream=stream)
+        stream.synchronize()
         ltrk.ltrk_timing_take()
         step_ms = []
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for i in range(args.warmup, nsteps):
+        for i in range(args.steps):
+            restore()
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ltrk.ltrk_track_f64(zs[i], ds[i], T, SPS_RING, integ, moms[i % 2], stream=stream)
+            ltrk.ltrk_track_f64(z_run, d_run, T, SPS_RING, integ, mom, stream=stream)
             stream.synchronize()
+            torch.cuda.synchronize()
             step_ms.append((time.perf_counter() - t0) * 1e3)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
+        elapsed = sum(step_ms) * 1e-3
         tm = ltrk.ltrk_timing_take()
         ltrk.ltrk_timing_enable(False)
     value = n * T * args.steps / elapsed
@@ -208,17 +222,18 @@ def bench_default(args):
         zh, zc = split_f32c(z0)
         dh, dc = split_f32c(dp0)
         f32 = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+        f32_run = [torch.empty_like(a) for a in f32]
         with torch.cuda.stream(stream):
-            ltrk.ltrk_track_f32c(*[a.clone() for a in f32], T, SPS_RING, integ, moms[0],
-                                 stream=stream)
-            stream.synchronize()
-            reps = 2
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                ltrk.ltrk_track_f32c(*[a.clone() for a in f32], T, SPS_RING, integ, moms[0],
-                                     stream=stream)
-            stream.synchronize()
-            f32_s = (time.perf_counter() - t0) / reps
+            reps, f32_s = 2, 0.0
+            for r in range(reps + 1):  # the first call builds the graph
+                for a, b in zip(f32_run, f32):
+                    a.copy_(b)
+                stream.synchronize()
+                t0 = time.perf_counter()
+                ltrk.ltrk_track_f32c(*f32_run, T, SPS_RING, integ, moms[0], stream=stream)
+                stream.synchronize()
+                if r:
+                    f32_s += (time.perf_counter() - t0) / reps
         v32 = n * T / f32_s
         extras["f32c"] = {"value": v32, "unit": "particle-turns/s", "ms_per_step": f32_s * 1e3,
                           "ratio_to_f64": v32 / value}
@@ -1030,7 +1045,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
                              "counters", "counters_f32c", "schemes", "rf2", "program", "6d",

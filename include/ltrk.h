@@ -310,9 +310,13 @@ int ltrk_tune_cache_save(const char* path);
 int ltrk_tune_cache_load(const char* path);
 
 /* Per-launch timing with HIP events. While enabled, every tracking and
- * finalize launch is bracketed by an event pair on its stream (graphs are
- * bypassed so each launch is visible). ltrk_timing_take synchronises the
- * recorded events, returns the totals and clears them. */
+ * finalize launch is timed by events on its stream: eager launches are
+ * bracketed by an event pair; a plan with use_graph replays a timed graph
+ * (cached apart from the untimed one) with event-record nodes between its
+ * segments of consecutive tracking or finalize launches, fresh events at
+ * every replay: a segment's time covers its launches and the short gaps
+ * between them, and the graph keeps its own launch cadence. ltrk_timing_take
+ * synchronises the recorded events, returns the totals and clears them. */
 typedef struct ltrk_timing {
     int64_t track_launches;
     double track_ms;

@@ -427,6 +427,8 @@ namespace {
 struct TimedLaunch {
   int kind;
   hipEvent_t a, b;
+  bool owns_a;  // false when a is the previous segment's b (a timed graph's chain)
+  int count;    // launches between a and b
 };
 std::mutex g_time_mu;
 bool g_time_on = false;
@@ -454,8 +456,12 @@ void timing_begin(hipStream_t s, int kind, void** token) {
   *token = nullptr;
   std::lock_guard<std::mutex> g(g_time_mu);
   if (!g_time_on) return;
-  TimedLaunch t{kind, pooled_event(), pooled_event()};
-  if (!t.a || !t.b) return;
+  TimedLaunch t{kind, pooled_event(), pooled_event(), true, 1};
+  if (!t.a || !t.b) {
+    if (t.a) g_event_pool.push_back(t.a);
+    if (t.b) g_event_pool.push_back(t.b);
+    return;
+  }
   hipEventRecord(t.a, s);
   g_timed.push_back(t);
   *token = reinterpret_cast<void*>(g_timed.size());
@@ -466,6 +472,28 @@ void timing_end(hipStream_t s, void* token) {
   std::lock_guard<std::mutex> g(g_time_mu);
   const size_t i = reinterpret_cast<size_t>(token) - 1;
   if (i < g_timed.size()) hipEventRecord(g_timed[i].b, s);
+}
+
+// Events for a timed graph replay: segment i (counts[i] launches of kind
+// kinds[i]) runs between ev[i] and ev[i + 1]. False (and no events) when
+// timing is off or events run out.
+bool timing_chain(const std::vector<int>& kinds, const std::vector<int>& counts,
+                  std::vector<hipEvent_t>* ev) {
+  std::lock_guard<std::mutex> g(g_time_mu);
+  ev->clear();
+  if (!g_time_on) return false;
+  for (size_t i = 0; i <= kinds.size(); ++i) {
+    hipEvent_t e = pooled_event();
+    if (!e) {
+      for (hipEvent_t x : *ev) g_event_pool.push_back(x);
+      ev->clear();
+      return false;
+    }
+    ev->push_back(e);
+  }
+  for (size_t i = 0; i < kinds.size(); ++i)
+    g_timed.push_back(TimedLaunch{kinds[i], (*ev)[i], (*ev)[i + 1], i == 0, counts[i]});
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +520,86 @@ hipError_t run_eager(const std::vector<Launch>& seq, hipStream_t s) {
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   std::vector<void*> owned;  // device tables that the graph's kernels read
+  // Timed graphs (built while ltrk_timing is on): the sequence in segments of
+  // consecutive launches of one kind (counts[i] launches of kind kinds[i]),
+  // an event-record node before the first segment and one after each
+  // (ev_nodes.size() == kinds.size() + 1); every replay sets fresh events
+  // into them, so the times come from the replayed graph itself. Events only
+  // between segments: an event-record node costs a few microseconds of
+  // launch cadence, so a segment's average per launch includes the short
+  // gaps between its launches and nothing else.
+  std::vector<hipGraphNode_t> ev_nodes;
+  std::vector<int> kinds, counts;
+  hipEvent_t placeholder = nullptr;
+  hipGraph_t graph = nullptr;  // a timed graph's nodes stay valid only with it
 };
+
+// Replay a cached graph; a timed one first gets a fresh event per node (the
+// placeholder when timing is off or out of events, so that events handed back
+// to the pool are never recorded again by an old replay).
+hipError_t launch_graph(GraphEntry& ge, hipStream_t s) {
+  if (!ge.ev_nodes.empty()) {
+    std::vector<hipEvent_t> ev;
+    const bool timed = timing_chain(ge.kinds, ge.counts, &ev);
+    for (size_t i = 0; i < ge.ev_nodes.size(); ++i) {
+      hipError_t e = hipGraphExecEventRecordNodeSetEvent(ge.exec, ge.ev_nodes[i],
+                                                         timed ? ev[i] : ge.placeholder);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipGraphLaunch(ge.exec, s);
+}
+
+// Build a timed graph for `seq`: each segment of consecutive launches of one
+// kind captured on s into a child graph, the segments chained through
+// event-record nodes.
+hipError_t build_timed_graph(const std::vector<Launch>& seq, hipStream_t s, GraphEntry* ge,
+                             hipGraph_t* out) {
+  *out = nullptr;
+  hipError_t e = hipEventCreate(&ge->placeholder);
+  if (e != hipSuccess) {
+    ge->placeholder = nullptr;
+    return e;
+  }
+  hipGraph_t g = nullptr;
+  if ((e = hipGraphCreate(&g, 0)) != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  if ((e = hipGraphAddEventRecordNode(&prev, g, nullptr, 0, ge->placeholder)) != hipSuccess) {
+    hipGraphDestroy(g);
+    return e;
+  }
+  ge->ev_nodes.push_back(prev);
+  for (size_t i = 0; i < seq.size();) {
+    size_t j = i;
+    while (j < seq.size() && seq[j].kind == seq[i].kind) ++j;
+    hipGraph_t child = nullptr;
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
+    hipError_t le = hipSuccess;
+    for (size_t k = i; k < j && le == hipSuccess; ++k) le = seq[k].fn(s);
+    e = hipStreamEndCapture(s, &child);
+    if (le != hipSuccess || e != hipSuccess || !child) {
+      if (child) hipGraphDestroy(child);
+      if (e == hipSuccess) e = le != hipSuccess ? le : hipErrorUnknown;
+      break;
+    }
+    hipGraphNode_t cn = nullptr, en = nullptr;
+    e = hipGraphAddChildGraphNode(&cn, g, &prev, 1, child);
+    hipGraphDestroy(child);
+    if (e != hipSuccess) break;
+    if ((e = hipGraphAddEventRecordNode(&en, g, &cn, 1, ge->placeholder)) != hipSuccess) break;
+    ge->ev_nodes.push_back(en);
+    ge->kinds.push_back(seq[i].kind);
+    ge->counts.push_back(static_cast<int>(j - i));
+    prev = en;
+    i = j;
+  }
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return e;
+  }
+  *out = g;
+  return hipSuccess;
+}
 
 struct Scratch {
   void* ptr = nullptr;
@@ -541,8 +648,20 @@ size_t scratch_cap_bytes() {
 void destroy_entry(GraphEntry& ge) {
   if (ge.exec) hipGraphExecDestroy(ge.exec);
   for (void* p : ge.owned) hipFree(p);
+  if (ge.placeholder) hipEventDestroy(ge.placeholder);
+  if (ge.graph) hipGraphDestroy(ge.graph);
+  ge.graph = nullptr;
   ge.exec = nullptr;
   ge.owned.clear();
+  ge.ev_nodes.clear();
+  ge.kinds.clear();
+  ge.counts.clear();
+  ge.placeholder = nullptr;
+}
+
+// Cache key of a graph: timed and untimed graphs of one sequence differ.
+std::string graph_key(const std::string& key) {
+  return key + (timing_on() ? 'T' : 'U');
 }
 
 // Drop every cached graph (device must be idle w.r.t. them).
@@ -643,46 +762,64 @@ bool stream_capturing(hipStream_t s) {
 // Run `seq` on s: from the graph cache under `key` when allowed, else eagerly.
 // `owned` device tables are kept alive with the cached graph (or freed after
 // an eager run once the stream is done with them).
-int execute(DeviceCtx& c, const std::string& key, std::vector<Launch>& seq, hipStream_t s,
+int execute(DeviceCtx& c, const std::string& key_in, std::vector<Launch>& seq, hipStream_t s,
             bool use_graph) {
-  const bool graph = use_graph && s != nullptr && !timing_on() && !stream_capturing(s);
+  const bool graph = use_graph && s != nullptr && !stream_capturing(s);
   if (!graph) {
     hipError_t e = run_eager(seq, s);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return LTRK_OK;
   }
+  const std::string key = graph_key(key_in);
+  const bool timed = key.back() == 'T';
   for (auto it = c.graphs.begin(); it != c.graphs.end(); ++it) {
     if (it->first == key) {
       c.graphs.splice(c.graphs.begin(), c.graphs, it);
-      hipError_t e = hipGraphLaunch(it->second.exec, s);
+      hipError_t e = launch_graph(it->second, s);
       if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
       return LTRK_OK;
     }
   }
-  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    e = run_eager(seq, s);
-    return e == hipSuccess ? LTRK_OK : fail_hip(e, "kernel launch");
-  }
-  hipError_t le = run_eager(seq, s);
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(s, &g);
-  if (le != hipSuccess || e != hipSuccess || !g) {
-    if (g) hipGraphDestroy(g);
-    return fail_hip(le != hipSuccess ? le : e, "graph capture");
-  }
   GraphEntry ge;
+  hipGraph_t g = nullptr;
+  hipError_t e;
+  if (timed) {
+    e = build_timed_graph(seq, s, &ge, &g);
+    if (e != hipSuccess) {
+      destroy_entry(ge);
+      return fail_hip(e, "timed graph capture");
+    }
+  } else {
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      e = run_eager(seq, s);
+      return e == hipSuccess ? LTRK_OK : fail_hip(e, "kernel launch");
+    }
+    hipError_t le = run_eager(seq, s);
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || e != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      return fail_hip(le != hipSuccess ? le : e, "graph capture");
+    }
+  }
   e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
-  if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+  if (timed)
+    ge.graph = g;  // its event-record node handles are set on every replay
+  else
+    hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ge.exec = nullptr;
+    destroy_entry(ge);
+    return fail_hip(e, "hipGraphInstantiate");
+  }
   if (c.graphs.size() >= c.max_graphs) {
     hipDeviceSynchronize();
     destroy_entry(c.graphs.back().second);
     c.graphs.pop_back();
   }
   c.graphs.emplace_front(key, std::move(ge));
-  e = hipGraphLaunch(c.graphs.front().second.exec, s);
+  e = launch_graph(c.graphs.front().second, s);
   if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
   return LTRK_OK;
 }
@@ -1257,12 +1394,13 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   for (const FinalizeDev& f : fin) key_add(key, f.out);
 
   // Device tables: found with a cached graph, else uploaded now.
-  const bool graph_ok = plan.use_graph && s && !timing_on() && !stream_capturing(s);
+  const bool graph_ok = plan.use_graph && s && !stream_capturing(s);
   if (graph_ok) {
+    const std::string gkey = graph_key(key);
     for (auto it = c.graphs.begin(); it != c.graphs.end(); ++it) {
-      if (it->first == key) {
+      if (it->first == gkey) {
         c.graphs.splice(c.graphs.begin(), c.graphs, it);
-        hipError_t e = hipGraphLaunch(it->second.exec, s);
+        hipError_t e = launch_graph(it->second, s);
         return e == hipSuccess ? LTRK_OK : fail_hip(e, "hipGraphLaunch");
       }
     }
@@ -1378,13 +1516,13 @@ static int timing_take(ltrk_timing* out) {
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, tl.a, tl.b);
     if (e != hipSuccess && rc == LTRK_OK) rc = fail_hip(e, "timing events");
     if (tl.kind == kTimeTrack) {
-      r.track_launches++;
+      r.track_launches += tl.count;
       r.track_ms += ms;
     } else {
-      r.finalize_launches++;
+      r.finalize_launches += tl.count;
       r.finalize_ms += ms;
     }
-    g_event_pool.push_back(tl.a);
+    if (tl.owns_a) g_event_pool.push_back(tl.a);
     g_event_pool.push_back(tl.b);
   }
   g_timed.clear();

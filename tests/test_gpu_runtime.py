@@ -1,6 +1,6 @@
 """Runtime services through the C ABI on the GPU: the autotuner and its cache
-file, per-launch event timing, and that a tuned plan still reproduces the
-oracle."""
+file, per-launch event timing (eager and inside replayed graphs), and that a
+tuned plan still reproduces the oracle."""
 import numpy as np
 import pytest
 
@@ -32,6 +32,57 @@ def test_timing_counts_launches(ltrk):
     ltrk.ltrk_set_plan()
     assert t["track_launches"] == 4 and t["finalize_launches"] == 1
     assert t["track_ms"] > 0 and t["finalize_ms"] > 0
+
+
+def test_timing_inside_replayed_graphs(ltrk):
+    """Per-launch timing of a hipGraph replay (event-record nodes between the
+    launches, fresh events per replay): results equal the eager run bit for
+    bit, every replay counts all its launches, and the launches' times add up
+    to no more than the whole call; with timing off again the untimed graph
+    runs and nothing is counted."""
+    z0, dp0 = gaussian_bunch(100_000, 0.2, 1e-3, 3)
+    s = torch.cuda.Stream()
+    T = 64
+
+    bufs = [torch.empty(z0.size, dtype=torch.float64, device="cuda") for _ in range(2)]
+    mom_d = torch.empty((T, 5), dtype=torch.float64, device="cuda")
+
+    def call(use_graph, fresh=False):
+        # the same buffers replay one cached graph; fresh ones build another
+        ltrk.ltrk_set_plan(16, 256, 4, use_graph)
+        if fresh:
+            z, dp = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+        else:
+            z, dp = bufs
+            z.copy_(torch.as_tensor(z0))
+            dp.copy_(torch.as_tensor(dp0))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom_d, stream=s)
+            b.record(s)
+        s.synchronize()
+        return z.cpu().numpy(), dp.cpu().numpy(), mom_d.cpu().numpy(), a.elapsed_time(b)
+
+    try:
+        ze, de, me, _ = call(0)
+        ltrk.ltrk_timing_enable(True)
+        ltrk.ltrk_timing_take()
+        for i in range(4):
+            z, dp, mom, wall_ms = call(1, fresh=(i == 2))
+            t = ltrk.ltrk_timing_take()
+            assert t["track_launches"] == 4 and t["finalize_launches"] == 1
+            assert t["track_ms"] > 0 and t["finalize_ms"] > 0
+            assert t["track_ms"] + t["finalize_ms"] <= wall_ms * 1.02 + 0.01
+            assert np.array_equal(z, ze) and np.array_equal(dp, de) and np.array_equal(mom, me)
+        ltrk.ltrk_timing_enable(False)
+        z, dp, mom, _ = call(1)
+        assert ltrk.ltrk_timing_take()["track_launches"] == 0
+        assert np.array_equal(z, ze) and np.array_equal(dp, de) and np.array_equal(mom, me)
+    finally:
+        ltrk.ltrk_timing_enable(False)
+        ltrk.ltrk_set_plan()
 
 
 def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
