@@ -1497,7 +1497,7 @@ static int shutdown_all() {
   hipSetDevice(prev);
   std::lock_guard<std::mutex> t(g_time_mu);
   for (auto& tl : g_timed) {
-    hipEventDestroy(tl.a);
+    if (tl.owns_a) hipEventDestroy(tl.a);
     hipEventDestroy(tl.b);
   }
   g_timed.clear();
