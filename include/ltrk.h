@@ -120,7 +120,11 @@ int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out);
  * z, dp: device arrays of n doubles, updated in place.
  * moments: device array of `turns` rows or NULL; row t receives the moments
  *   after turn t+1 (turn-0 moments: ltrk_moments_f64).
- * integrator: LTRK_EULER_CROMER .. LTRK_RK4. */
+ * integrator: LTRK_EULER_CROMER .. LTRK_RK4.
+ * Any finite z is valid (no aperture, no wrapping): the RF phase 2hz/C is
+ * reduced to [-1/2, 1/2] exactly, from the unrounded product while every
+ * particle of a 64 x ppl tile stays below 2^50 C/(2h) in magnitude for the
+ * launch, else from its FP64 rounding; a non-finite z gives NaN momenta. */
 int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_ring* ring,
                    int integrator, ltrk_moments* moments, void* stream);
 
