@@ -36,7 +36,12 @@ int64_t scratch_cols(int64_t W);
 int current_device(int* dev);
 
 // Plans: forced plan, tuned cache, built-in default (see runtime.hip).
-ltrk_plan choose_plan(int integrator, int dtype, int64_t n, bool batched);
+// is_default (optional) tells whether the built-in default was chosen.
+ltrk_plan choose_plan(int integrator, int dtype, int64_t n, bool batched,
+                      bool* is_default = nullptr);
+// Turns per launch of a default plan that computes moments, given the bytes
+// of one turn's moment partials (see tune.hip).
+int64_t default_turns_for_partials(int64_t turns_per_launch, int64_t bytes_per_row);
 
 // Launch timing hooks (no-ops unless ltrk_timing_enable(1)).
 bool timing_on();

@@ -881,8 +881,13 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   }
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  ltrk_plan plan = choose_plan(integrator, dtype, n, false);
+  bool default_plan = false;
+  ltrk_plan plan = choose_plan(integrator, dtype, n, false, &default_plan);
   if (ext) plan.ppl = std::max(plan.ppl, 4);  // extended kernels: 4 or 8 particles per lane
+  if (mom && default_plan)
+    plan.turns_per_launch = static_cast<int32_t>(default_turns_for_partials(
+        plan.turns_per_launch,
+        5 * waves_for(n, plan.ppl) * static_cast<int64_t>(sizeof(double))));
 
   BunchDev b;
   std::memset(&b, 0, sizeof(b));
@@ -1008,9 +1013,13 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
       return rc;
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false);
+  bool default_plan = false;
+  ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false, &default_plan);
   // six FP64 coordinates per particle: 4 particles per lane
   constexpr int ppl = 4;
+  if (mom && default_plan)
+    plan.turns_per_launch = static_cast<int32_t>(default_turns_for_partials(
+        plan.turns_per_launch, 15 * waves_for(n, ppl) * static_cast<int64_t>(sizeof(double))));
 
   Bunch6Dev b;
   std::memset(&b, 0, sizeof(b));
