@@ -336,11 +336,14 @@ int ltrk_timing_take(ltrk_timing* out);
  * moment rows, and `max_slots` job slots. A job is admitted when a slot is
  * free and its footprint fits in the arena; its state then stays on the device
  * until it is retired. Each ltrk_engine_step is one launch over a tile table
- * of every active job (mixed schemes and precisions) advancing each by
- * min(k, turns left), plus one moments finalize launch. Jobs admitted between
- * steps join the next step. Results equal those of ltrk_track_f64/f32c on the
- * same job with the same particles-per-lane. Not thread-safe: one host thread
- * drives an engine. */
+ * of every active job (mixed schemes and precisions, 8 particles per lane,
+ * heaviest schemes first) advancing each by min(k, turns left, what the
+ * moment-partial scratch holds), plus one moments finalize launch; the step's
+ * tables are uploaded on a copy stream of the engine. The partial scratch is
+ * 1 GiB beside the arena (LTRK_ENGINE_PARTIALS_MB sets another size in MiB).
+ * Jobs admitted between steps join the next step. Results equal those of
+ * ltrk_track_f64/f32c on the same job with 8 particles per lane. Not
+ * thread-safe: one host thread drives an engine. */
 typedef struct ltrk_engine ltrk_engine;
 
 /* A job. z0/dp0 (and z0_comp/dp0_comp for LTRK_F32C) are HOST arrays of the

@@ -24,7 +24,7 @@
 namespace ltrk {
 namespace {
 
-constexpr int kEnginePpl = 4;
+constexpr int kEnginePpl = 8;   // as the single-bunch default for large bunches
 constexpr int kEngineBlock = 256;
 constexpr int kDepth = 2;  // steps in flight
 
@@ -126,6 +126,7 @@ using namespace ltrk;
 struct ltrk_engine {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t copy = nullptr;  // step-table uploads, ahead of the steps that read them
   char* arena_base = nullptr;
   Arena arena;
   std::vector<Slot> slots;
@@ -140,6 +141,7 @@ struct ltrk_engine {
   TileDev* d_t[kDepth] = {nullptr, nullptr};
   FinalizeDev* d_f[kDepth] = {nullptr, nullptr};
   hipEvent_t buf_ev[kDepth] = {nullptr, nullptr};
+  hipEvent_t copy_ev[kDepth] = {nullptr, nullptr};
   bool buf_used[kDepth] = {false, false};
   int cur = 0;
   int64_t steps = 0;
@@ -174,6 +176,7 @@ void free_tables(ltrk_engine* e) {
 int ensure_tables(ltrk_engine* e, size_t nb, size_t nt) {
   if (nb <= e->cap_b && nt <= e->cap_t && e->h_b[0]) return LTRK_OK;
   hipError_t er = hipStreamSynchronize(e->stream);
+  if (er == hipSuccess && e->copy) er = hipStreamSynchronize(e->copy);
   if (er != hipSuccess) return fail_hip(er, "engine synchronise");
   free_tables(e);
   const size_t cb = std::max<size_t>(nb, e->slots.size());
@@ -219,6 +222,19 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
     }
   }
   if (act.empty()) return LTRK_OK;
+  // Heaviest tiles first (the launch's blocks are dispatched in tile order,
+  // so the cheap ones fill in behind and the launch ends on short blocks):
+  // jobs by per-particle-turn cost, a scheme's flops, F32C about 1.6 times
+  // FP64 (FP32/FP64 conversions and Kahan additions); a job's tiles stay
+  // together. The results do not depend on the order.
+  auto unit_cost = [&](int i) {
+    const Slot& s = e->slots[i];
+    static const double flops[4] = {30.0, 32.0, 76.0, 112.0};
+    const double f = s.integrator >= 0 && s.integrator < 4 ? flops[s.integrator] : 32.0;
+    return f * (s.dtype == LTRK_F32C ? 1.6 : 1.0);
+  };
+  std::stable_sort(act.begin(), act.end(),
+                   [&](int a, int b) { return unit_cost(a) > unit_cost(b); });
   // turns this step: bounded by the partial-sum scratch
   int64_t kcap = static_cast<int64_t>(e->partial_bytes / (sizeof(double) * 5)) /
                  std::max<int64_t>(cols_total, 1);
@@ -281,9 +297,13 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
     pt += s.n * rows;
   }
   const int nb = static_cast<int>(act.size());
-  if ((er = hipMemcpyAsync(e->d_b[b], hb, nb * sizeof(BunchDev), hipMemcpyHostToDevice, e->stream)) != hipSuccess ||
-      (er = hipMemcpyAsync(e->d_t[b], ht, t * sizeof(TileDev), hipMemcpyHostToDevice, e->stream)) != hipSuccess ||
-      (er = hipMemcpyAsync(e->d_f[b], hf, nb * sizeof(FinalizeDev), hipMemcpyHostToDevice, e->stream)) != hipSuccess)
+  // The uploads run on the copy stream while the previous steps compute (the
+  // buffers were last read by the step two back, which buf_ev[b] waited for)
+  if ((er = hipMemcpyAsync(e->d_b[b], hb, nb * sizeof(BunchDev), hipMemcpyHostToDevice, e->copy)) != hipSuccess ||
+      (er = hipMemcpyAsync(e->d_t[b], ht, t * sizeof(TileDev), hipMemcpyHostToDevice, e->copy)) != hipSuccess ||
+      (er = hipMemcpyAsync(e->d_f[b], hf, nb * sizeof(FinalizeDev), hipMemcpyHostToDevice, e->copy)) != hipSuccess ||
+      (er = hipEventRecord(e->copy_ev[b], e->copy)) != hipSuccess ||
+      (er = hipStreamWaitEvent(e->stream, e->copy_ev[b], 0)) != hipSuccess)
     return fail_hip(er, "engine table upload");
   void* tok = nullptr;
   timing_begin(e->stream, kTimeTrack, &tok);
@@ -320,14 +340,18 @@ void engine_free(ltrk_engine* e) {
   if (!e) return;
   hipSetDevice(e->device);
   if (e->stream) hipStreamSynchronize(e->stream);
+  if (e->copy) hipStreamSynchronize(e->copy);
   free_tables(e);
   for (Slot& s : e->slots)
     if (s.last) hipEventDestroy(s.last);
-  for (int i = 0; i < kDepth; ++i)
+  for (int i = 0; i < kDepth; ++i) {
     if (e->buf_ev[i]) hipEventDestroy(e->buf_ev[i]);
+    if (e->copy_ev[i]) hipEventDestroy(e->copy_ev[i]);
+  }
   if (e->partials) hipFree(e->partials);
   if (e->arena_base) hipFree(e->arena_base);
   if (e->stream) hipStreamDestroy(e->stream);
+  if (e->copy) hipStreamDestroy(e->copy);
   delete e;
 }
 
@@ -359,7 +383,8 @@ int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk
     e->device = device;
     int rc = LTRK_OK;
     if ((er = hipSetDevice(device)) != hipSuccess ||
-        (er = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking)) != hipSuccess) {
+        (er = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking)) != hipSuccess ||
+        (er = hipStreamCreateWithFlags(&e->copy, hipStreamNonBlocking)) != hipSuccess) {
       rc = fail_hip(er, "engine stream");
     }
     const size_t arena = round_up(static_cast<size_t>(hbm_budget_bytes), 256);
@@ -368,8 +393,12 @@ int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk
       rc = fail(LTRK_ENOMEM, "engine arena of %zu bytes", arena);
     }
     if (rc == LTRK_OK) {
+      // 1 GiB (of 288 GB): a step advances every active job by min(k, what
+      // the scratch holds) turns, so a larger scratch means fewer, longer
+      // steps (measured at 300 requests: 256 MiB 6.6e11, 1 GiB 7.0e11
+      // particle-turns/s, the GPU busy 94% and 98% of the run)
       const char* env = std::getenv("LTRK_ENGINE_PARTIALS_MB");
-      long mb = env ? std::atol(env) : 256;
+      long mb = env ? std::atol(env) : 1024;
       if (mb < 1) mb = 1;
       e->partial_bytes = static_cast<size_t>(mb) << 20;
       if (hipMalloc(reinterpret_cast<void**>(&e->partials), e->partial_bytes) != hipSuccess) {
@@ -383,7 +412,9 @@ int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk
       for (Slot& s : e->slots)
         if (hipEventCreateWithFlags(&s.last, hipEventDisableTiming) != hipSuccess) rc = fail(LTRK_EDEVICE, "engine events");
       for (int i = 0; i < kDepth && rc == LTRK_OK; ++i)
-        if (hipEventCreateWithFlags(&e->buf_ev[i], hipEventDisableTiming) != hipSuccess) rc = fail(LTRK_EDEVICE, "engine events");
+        if (hipEventCreateWithFlags(&e->buf_ev[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e->copy_ev[i], hipEventDisableTiming) != hipSuccess)
+          rc = fail(LTRK_EDEVICE, "engine events");
     }
     if (rc != LTRK_OK) {
       engine_free(e);

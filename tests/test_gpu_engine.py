@@ -30,7 +30,8 @@ JOBS = [(1000, 250, "leapfrog", "f64"), (70_001, 90, "ruth4", "f32c"),
 
 
 def alone(ltrk, n, turns, integ, dtype, z0, dp0):
-    ltrk.ltrk_set_plan(128, 256, 4, 0)
+    # the engine's tiles hold 8 particles per lane; the same plan alone
+    ltrk.ltrk_set_plan(128, 256, 8, 0)
     mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda")
     if dtype == "f64":
         z, dp = dev(z0, torch.float64), dev(dp0, torch.float64)
