@@ -31,6 +31,10 @@ enum DType : int32_t { kF64 = LTRK_F64, kF32C = LTRK_F32C };
 // Terms of the polynomial for sin(pi r) / r in r^2 (see sinpi_coeffs.h).
 constexpr int kSinTerms = 8;
 
+// |s z| below which a wave may reduce the RF phase from the unrounded
+// product (the reduction itself holds to 2^51; a factor 2 of margin).
+constexpr double kExactRange = 0x1p50;
+
 // Per-bunch coefficients, derived on the host in FP64 once per call.
 struct Coeffs {
   double half_rev_per_m;       // s = 2h/C: k z = pi * (s z)

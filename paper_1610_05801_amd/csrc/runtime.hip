@@ -131,7 +131,7 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
               // z (stages included) by at most |D| (|delta| + |A|)
       break;
   }
-  c->z_exact = 0x1p50 / c->half_rev_per_m;
+  c->z_exact = kExactRange / c->half_rev_per_m;
   c->reach_d = drift_sum * std::fabs(D);
   c->reach_k = kick_sum * std::fabs(A);
   static_assert(kSinTerms == kSinPiTerms, "polynomial length");

@@ -31,7 +31,6 @@ namespace ltrk {
 //     |s z| < 2^51 r is unbounded, so callers use it only for waves whose
 //     positions in_exact_range() has bounded for the whole launch.
 constexpr double kRoundMagic = 0x1.8p52;
-constexpr double kExactRange = 0x1p50;  // |s z| bound of the exact-product reduction, 2x margin
 
 struct KickTerms {
   double r, p;
