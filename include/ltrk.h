@@ -298,7 +298,11 @@ typedef struct ltrk_plan {
 
 /* Force one plan for all following calls of this process (NULL: back to
  * automatic plans from the tuning cache or the built-in default). EINVAL for
- * values outside the ranges above. */
+ * values outside the ranges above. Forced and tuned plans are used as given;
+ * the built-in default (1024 turns per launch) is lowered, for calls that
+ * compute moments, to the largest power of two (at least 64) whose moment
+ * partials of one launch stay within 192 MiB, e.g. 256 turns at 1e7
+ * particles. */
 int ltrk_set_plan(const ltrk_plan* plan);
 
 /* The plan a call with these parameters would use now. */
