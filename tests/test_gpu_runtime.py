@@ -34,6 +34,30 @@ def test_timing_counts_launches(ltrk):
     assert t["track_ms"] > 0 and t["finalize_ms"] > 0
 
 
+def test_default_plan_follows_the_moment_partials(ltrk):
+    """The default plan's 1024 turns per launch are lowered for calls with
+    moments so that one launch's partial rows stay within 192 MiB: at 1e7
+    particles (8 per lane, 19532 wave tiles, 781 KB per row) 256 turns; at
+    1e6 (78 KB per row) the full 1024; without moments nothing changes."""
+    ltrk.ltrk_set_plan()
+
+    def launches(n, turns, moments):
+        z = torch.zeros(n, dtype=torch.float64, device="cuda")
+        dp = torch.zeros(n, dtype=torch.float64, device="cuda")
+        mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda") if moments else None
+        ltrk.ltrk_timing_enable(True)
+        ltrk.ltrk_timing_take()
+        ltrk.ltrk_track_f64(z, dp, turns, SPS_RING, "leapfrog", mom)
+        t = ltrk.ltrk_timing_take()
+        ltrk.ltrk_timing_enable(False)
+        return t["track_launches"]
+
+    assert ltrk.ltrk_get_plan("leapfrog", "f64", 10_000_000)["turns_per_launch"] == 1024
+    assert launches(10_000_000, 1024, True) == 4
+    assert launches(10_000_000, 1024, False) == 1
+    assert launches(1_000_000, 2048, True) == 2
+
+
 def test_timing_inside_replayed_graphs(ltrk):
     """Per-launch timing of a hipGraph replay (event-record nodes between the
     launches, fresh events per replay): results equal the eager run bit for
