@@ -635,14 +635,14 @@ DeviceCtx& ctx_for(int dev) {
   return *p;
 }
 
+// Cap of one call's moment-partial scratch, LTRK_SCRATCH_MB (MiB, at least
+// 16; default 1 GiB), read at every call: runs that need more rows are
+// finalized in chunks.
 size_t scratch_cap_bytes() {
-  static size_t cap = [] {
-    const char* e = std::getenv("LTRK_SCRATCH_MB");
-    long mb = e ? std::atol(e) : 1024;
-    if (mb < 16) mb = 16;
-    return static_cast<size_t>(mb) << 20;
-  }();
-  return cap;
+  const char* e = std::getenv("LTRK_SCRATCH_MB");
+  long mb = e ? std::atol(e) : 1024;
+  if (mb < 16) mb = 16;
+  return static_cast<size_t>(mb) << 20;
 }
 
 void destroy_entry(GraphEntry& ge) {
