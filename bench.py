@@ -1,6 +1,6 @@
 """Benchmark of the longitudinal tracking hot path on one MI355X.
 
-Default (the driver's contract): one step = tracking 1e6 particles for 1e4
+Default: one step = tracking 1e6 particles for 1e4
 turns with FP64 leap-frog and moments after every turn (host constants, the
 fused turn kernels and the moment finalize: the whole hot path) of a seeded
 Gaussian bunch already resident in HBM, restored from a resident copy before
@@ -48,7 +48,7 @@ def _sin_terms() -> int:
         return int(re.search(r"kSinPiTerms = (\d+);", f.read()).group(1))
 
 
-# Algorithmic FP64 flops per particle-turn (FMA = 2), see the design doc:
+# Algorithmic FP64 flops per particle-turn (FMA = 2), the method's count:
 # sin(k z) = phase multiply + reduction subtract + r^2 + (terms - 1) FMA + final
 # multiply by r.
 SIN_FLOPS = 4 + 2 * (_sin_terms() - 1)
@@ -1065,9 +1065,9 @@ def main():
                     help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(particles would shard by range with one final moment-sum reduction; "
-              "see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: libltrk has no multi-GPU path "
+              "(particles would shard by range with one final moment-sum reduction)",
+              file=sys.stderr)
         sys.exit(2)
     if args.summarize:
         summarize_counters(args.summarize[0], args.summarize[1], args.summarize[2],
