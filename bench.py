@@ -7,9 +7,11 @@ Gaussian bunch already resident in HBM, restored from a resident copy before
 each step outside the step's timer (each step is bracketed by device
 synchronisations; `value` is K steps of particle-turns over the sum of their
 times). Per-launch kernel times come from HIP events inside the replayed
-launch graph. Prints ONE JSON line on stdout; progress goes to stderr.
+launch graph. The default 20 warm-up steps (~0.15 s) cover the graph build
+and the first steps of a process, over which the GPU clock is still rising.
+Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 6]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 20]
 
 Other workloads (--workload): unfused (one launch per turn, HBM roofline
 sweep), precision (FP32+Kahan vs FP64, 1e7 particles), batched (256 uneven
@@ -1045,7 +1047,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
                              "counters", "counters_f32c", "schemes", "rf2", "program", "6d",

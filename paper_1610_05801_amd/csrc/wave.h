@@ -120,7 +120,6 @@ __device__ __forceinline__ bool in_exact_range(const Coeffs& c, const double (&z
   return __all(ok);
 }
 
-// Kahan-compensated x += inc with the running compensation c (value = x - c).
 // ---------------------------------------------------------------------------
 // Moment sums
 
