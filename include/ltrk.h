@@ -288,7 +288,13 @@ int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int int
 /* Launch plan. turns_per_launch K: turns fused per kernel launch (1 = one
  * launch per turn, the unfused form); block: threads per block (64, 128 or
  * 256); ppl: particles per lane (1, 2, 4 or 8); use_graph: replay the launch
- * sequence from a cached hipGraph (streams other than NULL only). */
+ * sequence from a cached hipGraph (streams other than NULL only). A call of
+ * more launches than the environment variable LTRK_MAX_GRAPH_LAUNCHES (read
+ * at every call; default 32768, at least 16) is never captured: its launches
+ * are enqueued as they are generated, in pieces of that length, with the same
+ * results. The moment partials of one call take at most LTRK_SCRATCH_MB MiB
+ * (read at every call; default 1024, at least 16); longer runs are finalized
+ * in chunks of turns, with the same results. */
 typedef struct ltrk_plan {
     int32_t turns_per_launch;
     int32_t block;

@@ -763,7 +763,8 @@ bool stream_capturing(hipStream_t s) {
 // `owned` device tables are kept alive with the cached graph (or freed after
 // an eager run once the stream is done with them).
 int execute(DeviceCtx& c, const std::string& key_in, std::vector<Launch>& seq, hipStream_t s,
-            bool use_graph) {
+            bool use_graph, GraphEntry** made = nullptr) {
+  if (made) *made = nullptr;
   const bool graph = use_graph && s != nullptr && !stream_capturing(s);
   if (!graph) {
     hipError_t e = run_eager(seq, s);
@@ -819,9 +820,67 @@ int execute(DeviceCtx& c, const std::string& key_in, std::vector<Launch>& seq, h
     c.graphs.pop_back();
   }
   c.graphs.emplace_front(key, std::move(ge));
+  if (made) *made = &c.graphs.front().second;
   e = launch_graph(c.graphs.front().second, s);
   if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
   return LTRK_OK;
+}
+
+// Launches of one call above which the call runs eagerly, its sequence
+// launched in pieces of this length as it is generated (LTRK_MAX_GRAPH_LAUNCHES,
+// at least 16, read at every call; default 32768): a graph of that many nodes
+// takes long to build and saves nothing on launches of a millisecond, and a
+// long sequence is never held whole in host memory.
+size_t max_graph_launches() {
+  const char* e = std::getenv("LTRK_MAX_GRAPH_LAUNCHES");
+  long v = e ? std::atol(e) : 32768;
+  if (v < 16) v = 16;
+  return static_cast<size_t>(v);
+}
+
+// Launches of a run of `turns` turns in chunks of `rows` (the moment finalize
+// cadence), `per` turns per launch, plus `extra` launches after each chunk.
+int64_t count_launches(int64_t turns, int64_t rows, int64_t per, int64_t extra) {
+  auto in = [&](int64_t len) { return (len + per - 1) / per + extra; };
+  return (turns / rows) * in(rows) + (turns % rows ? in(turns % rows) : 0);
+}
+
+// A call's launch sequence: collected for execute(), or, when `expected`
+// exceeds max_graph_launches(), launched eagerly in pieces as it is pushed.
+class LaunchSeq {
+ public:
+  LaunchSeq(int64_t expected, hipStream_t s)
+      : piece_(max_graph_launches()), eager_(expected > static_cast<int64_t>(piece_)), s_(s) {}
+  bool eager() const { return eager_; }
+  std::vector<Launch>& seq() { return seq_; }
+  void push(Launch l) {
+    seq_.push_back(std::move(l));
+    if (eager_ && seq_.size() >= piece_) flush();
+  }
+  // Launch what is pending (eager mode); the first launch error, if any.
+  hipError_t flush() {
+    if (err_ == hipSuccess && !seq_.empty()) err_ = run_eager(seq_, s_);
+    seq_.clear();
+    return err_;
+  }
+
+ private:
+  size_t piece_;
+  bool eager_;
+  hipStream_t s_;
+  hipError_t err_ = hipSuccess;
+  std::vector<Launch> seq_;
+};
+
+// Run a collected or streamed sequence to its end.
+int finish(DeviceCtx& c, const std::string& key, LaunchSeq& ls, hipStream_t s, bool use_graph,
+           GraphEntry** made = nullptr) {
+  if (made) *made = nullptr;
+  if (ls.eager()) {
+    hipError_t e = ls.flush();
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "kernel launch");
+  }
+  return execute(c, key, ls.seq(), s, use_graph, made);
 }
 
 template <typename T>
@@ -945,7 +1004,7 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   key_add(key, mom);
   key_add(key, scratch);
 
-  std::vector<Launch> seq;
+  LaunchSeq seq(count_launches(turns, rows, K, mom ? 1 : 0), s);
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
     for (int64_t j = 0; j < len; j += K) {
@@ -956,17 +1015,17 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       const int ppl = plan.ppl, block = plan.block;
       const int32_t turn0 = static_cast<int32_t>(c0 + j);
       if (use_program)
-        seq.push_back({kTimeTrack, [bl, ce, prog_dev, turn0, row0, ppl, block, accel](
+        seq.push({kTimeTrack, [bl, ce, prog_dev, turn0, row0, ppl, block, accel](
                                        hipStream_t st) {
                          return launch_track_prog(bl, ce, static_cast<const double*>(prog_dev),
                                                   turn0, row0, ppl, block, accel, st);
                        }});
       else if (ext)
-        seq.push_back({kTimeTrack, [bl, ce, row0, ppl, block](hipStream_t st) {
+        seq.push({kTimeTrack, [bl, ce, row0, ppl, block](hipStream_t st) {
                          return launch_track_rf2(bl, ce, row0, ppl, block, st);
                        }});
       else
-        seq.push_back({kTimeTrack, [bl, row0, ppl, block](hipStream_t st) {
+        seq.push({kTimeTrack, [bl, row0, ppl, block](hipStream_t st) {
                          return launch_track_single(bl, row0, ppl, block, st);
                        }});
     }
@@ -980,10 +1039,10 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       f.n = n;
       f.out = mom + c0;
       f.rows = static_cast<int32_t>(len);
-      seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+      seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
     }
   }
-  return execute(c, key, seq, s, plan.use_graph != 0);
+  return finish(c, key, seq, s, plan.use_graph != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,7 +1123,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   key_add(key, mom);
   key_add(key, scratch);
 
-  std::vector<Launch> seq;
+  LaunchSeq seq(count_launches(turns, rows, K, mom ? 3 : 0), s);
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
     for (int64_t j = 0; j < len; j += K) {
@@ -1073,7 +1132,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
       bl.partials = static_cast<double*>(scratch);
       const int32_t row0 = static_cast<int32_t>(j);
       const int block = plan.block;
-      seq.push_back({kTimeTrack, [bl, c6, row0, block](hipStream_t st) {
+      seq.push({kTimeTrack, [bl, c6, row0, block](hipStream_t st) {
                        return launch_track_6d(bl, c6, row0, ppl, block, st);
                      }});
     }
@@ -1090,11 +1149,11 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
         f.out = mom + c0 * 3 + p;
         f.rows = static_cast<int32_t>(len);
         f.planes = 3;
-        seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+        seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
       }
     }
   }
-  return execute(c, key, seq, s, plan.use_graph != 0);
+  return finish(c, key, seq, s, plan.use_graph != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1195,10 +1254,11 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
 
   // A(t) kicks with turn t-1's potential and writes moment row t-1; row r
   // lives at r - c0 in the chunk [c0, c0 + rows) finalized once complete.
-  std::vector<Launch> seq;
+  // 2 turns + 2 launches, and a finalize after each chunk of rows.
+  LaunchSeq seq(2 * turns + 2 + (mom ? (turns + rows - 1) / rows : 0), s);
   auto turn_launch = [&](int phase, int64_t row) {
     const int32_t local = static_cast<int32_t>(row < 0 ? 0 : row % rows);
-    seq.push_back({kTimeTrack, [b, ce, w, phase, local, block, grid, ppl](hipStream_t st) {
+    seq.push({kTimeTrack, [b, ce, w, phase, local, block, grid, ppl](hipStream_t st) {
                      return launch_wake_turn(b, ce, w, phase, local, ppl, block, grid, st);
                    }});
     if (mom && row >= 0 && (row % rows == rows - 1 || row == turns - 1)) {
@@ -1212,13 +1272,13 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
       f.n = n;
       f.out = mom + c0;
       f.rows = static_cast<int32_t>(row - c0 + 1);
-      seq.push_back({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
+      seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
     }
   };
   auto potential = [&]() {
-    seq.push_back({kTimeFinalize, [w](hipStream_t st) { return launch_wake_potential(w, st); }});
+    seq.push({kTimeFinalize, [w](hipStream_t st) { return launch_wake_potential(w, st); }});
   };
-  seq.push_back({kTimeFinalize, [w](hipStream_t st) { return launch_wake_zero(w, st); }});
+  seq.push({kTimeFinalize, [w](hipStream_t st) { return launch_wake_zero(w, st); }});
   turn_launch(0, -1);
   for (int64_t t = 1; t < turns; ++t) {
     potential();
@@ -1226,7 +1286,7 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
   }
   potential();
   turn_launch(2, turns - 1);
-  return execute(c, key, seq, s, plan.use_graph != 0);
+  return finish(c, key, seq, s, plan.use_graph != 0);
 }
 
 static int moments_single(const void* z, const void* dp, const void* zc, const void* dc,
@@ -1403,7 +1463,9 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   for (const FinalizeDev& f : fin) key_add(key, f.out);
 
   // Device tables: found with a cached graph, else uploaded now.
-  const bool graph_ok = plan.use_graph && s && !stream_capturing(s);
+  const int64_t expected = count_launches(turns, rows, K, fin.empty() ? 0 : 1);
+  const bool graph_ok = plan.use_graph && s && !stream_capturing(s) &&
+                        expected <= static_cast<int64_t>(max_graph_launches());
   if (graph_ok) {
     const std::string gkey = graph_key(key);
     for (auto it = c.graphs.begin(); it != c.graphs.end(); ++it) {
@@ -1438,7 +1500,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
     return fail_hip(e, "upload bunch tables");
   }
 
-  std::vector<Launch> seq;
+  LaunchSeq seq(graph_ok ? 0 : expected, s);
   const int64_t ntiles = static_cast<int64_t>(tiles.size());
   const int nf = static_cast<int>(fin.size());
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
@@ -1448,20 +1510,20 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
       const int32_t row0 = static_cast<int32_t>(j);
       const ltrk_plan p = plan;
       const bool m = any_mom;
-      seq.push_back({kTimeTrack, [=](hipStream_t st) {
+      seq.push({kTimeTrack, [=](hipStream_t st) {
                        return launch_track_tiles(d_b, d_t, ntiles, integrator, dtype, tk, row0,
                                                  p.ppl, p.block, m, st);
                      }});
     }
     if (nf > 0) {
       const int mr = static_cast<int>(len);
-      seq.push_back({kTimeFinalize, [=](hipStream_t st) {
+      seq.push({kTimeFinalize, [=](hipStream_t st) {
                        return launch_finalize_multi(d_f, nf, mr, c0, max_groups, st);
                      }});
     }
   }
   if (!graph_ok) {
-    e = run_eager(seq, s);
+    e = seq.eager() ? seq.flush() : run_eager(seq.seq(), s);
     // tables are freed once the stream has consumed them
     hipError_t se = hipStreamSynchronize(s);
     hipFree(tables);
@@ -1469,13 +1531,16 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
     if (se != hipSuccess) return fail_hip(se, "batched run");
     return LTRK_OK;
   }
-  rc = execute(c, key, seq, s, true);
-  if (rc) {
+  GraphEntry* made = nullptr;
+  rc = execute(c, key, seq.seq(), s, true, &made);
+  if (rc || !made) {
+    // failed, or run eagerly (capture unavailable): the tables are done with
+    // once the stream is
     hipStreamSynchronize(s);
     hipFree(tables);
     return rc;
   }
-  c.graphs.front().second.owned.push_back(tables);
+  made->owned.push_back(tables);
   return LTRK_OK;
 }
 

@@ -109,6 +109,64 @@ def test_timing_inside_replayed_graphs(ltrk):
         ltrk.ltrk_set_plan()
 
 
+def test_long_sequences_run_eagerly_in_pieces(ltrk, monkeypatch):
+    """A call of more launches than LTRK_MAX_GRAPH_LAUNCHES (here 16) is not
+    captured into a graph: its launches are enqueued eagerly, in pieces, as
+    they are generated. Every tracking entry point then gives the results of
+    the same call replayed from a graph bit for bit (single bunch with
+    moments, 6-D, wake, batched; 51 to 123 launches per call)."""
+    from tests.test_gpu_6d import KEYS, RF as RF6, TW, state, twiss_abi
+    from tests.test_gpu_wake import RES, RF as RFW
+    from synth import BunchSpec, ring_for
+    s = torch.cuda.Stream()
+    T, Tw = 200, 60
+    z0, dp0 = gaussian_bunch(5000, 0.2, 1e-3, 11)
+    st6 = state(3000, 12)
+    zw0, dw0 = gaussian_bunch(4000, 0.15, 6e-4, 13)
+    specs = [BunchSpec(700, 2e6, 4620.0, 1e-3, 14), BunchSpec(2500, 5e6, 9240.0, 6e-4, 15)]
+    wake = dict(RES, n_slices=64)
+
+    def f64(a):
+        return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float64)
+
+    def run_all():
+        ltrk.ltrk_set_plan(4, 256, 4, 1)
+        out = []
+        with torch.cuda.stream(s):
+            z, dp = f64(z0), f64(dp0)
+            mom = torch.empty((T, 5), dtype=torch.float64, device="cuda")
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom, stream=s)
+            d6 = [f64(st6[k]) for k in KEYS]
+            m6 = torch.empty((T, 3, 5), dtype=torch.float64, device="cuda")
+            ltrk.ltrk_track_6d_f64(*d6, T, RF6, twiss_abi(TW), "ruth4", m6, stream=s)
+            zw, dw = f64(zw0), f64(dw0)
+            mw = torch.empty((Tw, 5), dtype=torch.float64, device="cuda")
+            ltrk.ltrk_track_wake_f64(zw, dw, Tw, RFW, wake, "leapfrog", mw, stream=s)
+            bunches = []
+            for sp in specs:
+                bz, bd = gaussian_bunch(sp.n, 0.1, sp.sigma_dp, sp.seed)
+                bunches.append(dict(z=f64(bz), dp=f64(bd), ring=ring_for(sp),
+                                    moments=torch.empty((T, 5), dtype=torch.float64,
+                                                        device="cuda")))
+            ltrk.ltrk_track_batched(bunches, T, "euler_cromer", "f64", stream=s)
+        s.synchronize()
+        out = [z, dp, mom, *d6, m6, zw, dw, mw]
+        for b in bunches:
+            out += [b["z"], b["dp"], b["moments"]]
+        return [t.cpu().numpy() for t in out]
+
+    try:
+        graph = run_all()
+        monkeypatch.setenv("LTRK_MAX_GRAPH_LAUNCHES", "16")
+        pieces = run_all()
+    finally:
+        monkeypatch.delenv("LTRK_MAX_GRAPH_LAUNCHES", raising=False)
+        ltrk.ltrk_set_plan()
+    assert len(graph) == len(pieces) == 19
+    for a, b in zip(graph, pieces):
+        assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
 def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
     n = 200_000
     best = ltrk.ltrk_autotune("leapfrog", "f64", n)
