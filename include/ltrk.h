@@ -385,8 +385,10 @@ int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk
 /* Bytes of arena a job needs: state (16 B per particle) + moment rows (40 B
  * per turn), each rounded up to 256 B. */
 int ltrk_engine_footprint(const ltrk_job* job, int64_t* bytes);
-/* Admit a job: LTRK_EAGAIN if no slot is free or the arena has no block large
- * enough now; EINVAL if the job can never fit or is malformed. */
+/* Admit a job: LTRK_EAGAIN if no slot is free, the arena has no block large
+ * enough now, or the running jobs and this one would need more moment-partial
+ * columns (one per 512 particles) than the partial scratch holds; EINVAL if
+ * the job can never fit (arena or partial scratch alone) or is malformed. */
 int ltrk_engine_admit(ltrk_engine* e, const ltrk_job* job, int* slot);
 /* Advance every active job by up to k turns (1 <= k <= 4096). `stream` NULL
  * uses the engine's own stream; otherwise the step is ordered after prior

@@ -449,6 +449,19 @@ int ltrk_engine_admit(ltrk_engine* e, const ltrk_job* job, int* slot) {
         break;
       }
     if (free_slot < 0) return fail(LTRK_EAGAIN, "no free slot");
+    // A step needs one row of moment partials per active job in the partial
+    // scratch (it then advances them by as many turns as the scratch holds),
+    // so the jobs that are still running must fit in it together.
+    const int64_t cap_cols = static_cast<int64_t>(e->partial_bytes / (5 * sizeof(double)));
+    const int64_t cols = scratch_cols(waves_for(job->n, kEnginePpl));
+    if (cols > cap_cols)
+      return fail(LTRK_EINVAL, "job needs %lld moment-partial columns, the engine holds %lld "
+                  "(LTRK_ENGINE_PARTIALS_MB)", (long long)cols, (long long)cap_cols);
+    int64_t cols_running = 0;
+    for (const Slot& o : e->slots)
+      if (o.used && !o.cancelled && o.done_turns < o.turns) cols_running += scratch_cols(o.waves);
+    if (cols_running + cols > cap_cols)
+      return fail(LTRK_EAGAIN, "moment-partial scratch taken by running jobs");
     size_t off = 0;
     if (!e->arena.alloc(need, &off)) return fail(LTRK_EAGAIN, "arena has no free block of %zu bytes", need);
     if ((rc = with_device(e))) {

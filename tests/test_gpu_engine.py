@@ -127,3 +127,39 @@ def test_engine_admission_limits(ltrk):
     z2, dp2, mom2 = eng.result(c)
     assert np.array_equal(z, z2) and np.array_equal(mom, mom2)
     eng.close()
+
+
+def test_engine_admission_by_partial_scratch(ltrk, monkeypatch):
+    """Running jobs share the engine's moment-partial scratch (here 1 MiB:
+    26214 columns of 5 doubles, one column per 512 particles): a job that
+    needs more than all of it is refused for good, one that does not fit
+    beside the running jobs waits (EngineBusy) until they are done, and steps
+    never run out of scratch."""
+    monkeypatch.setenv("LTRK_ENGINE_PARTIALS_MB", "1")
+    try:
+        eng = ltrk.Engine(hbm_budget_bytes=512 << 20, max_slots=4)
+    finally:
+        monkeypatch.delenv("LTRK_ENGINE_PARTIALS_MB", raising=False)
+    rng = np.random.default_rng(3)
+    na, nb_, nc = 6_000_000, 9_000_000, 15_000_000   # ~11.7k, ~17.6k, ~29.3k columns
+    za, da = 0.2 * rng.standard_normal(na), 1e-3 * rng.standard_normal(na)
+    with pytest.raises(ltrk.LtrkError) as bad:
+        eng.admit(nc, 4, SPS_RING, "leapfrog", "f64", np.zeros(nc), np.zeros(nc))
+    assert not isinstance(bad.value, ltrk.EngineBusy)
+    a = eng.admit(na, 4, SPS_RING, "leapfrog", "f64", za, da)
+    zb = 0.2 * rng.standard_normal(nb_)
+    with pytest.raises(ltrk.EngineBusy):
+        eng.admit(nb_, 4, SPS_RING, "leapfrog", "f64", zb, np.zeros(nb_))
+    while not eng.poll(a):
+        eng.step(4)
+        torch.cuda.synchronize()
+    b = eng.admit(nb_, 4, SPS_RING, "leapfrog", "f64", zb, np.zeros(nb_))
+    while not eng.poll(b):
+        eng.step(4)
+        torch.cuda.synchronize()
+    z, dp, mom = eng.result(a)
+    assert np.isfinite(z).all() and np.isfinite(mom).all()
+    _, _, mom_b = eng.result(b)
+    assert np.isfinite(mom_b).all()
+    eng.close()
+
