@@ -319,7 +319,10 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
  * floor(log2 n)). `best` (host, may be NULL) receives it. */
 int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best);
 
-/* Save / load the tuning cache as text. */
+/* Save / load the tuning cache as text, one entry per line: arch integrator
+ * dtype log2(n) batched K block ppl graph. Loading merges the file's valid
+ * entries into the cache and skips lines that do not parse; EINVAL if the
+ * file cannot be opened. */
 int ltrk_tune_cache_save(const char* path);
 int ltrk_tune_cache_load(const char* path);
 

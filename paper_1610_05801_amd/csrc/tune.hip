@@ -311,8 +311,8 @@ int ltrk_tune_cache_load(const char* path) {
   if (!path) return fail(LTRK_EINVAL, "path is NULL");
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(LTRK_EINVAL, "cannot open %s", path);
+  // Lines that do not parse as a valid entry are skipped.
   char line[256];
-  int loaded = 0;
   std::lock_guard<std::mutex> g(g_plan_mu);
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
@@ -323,11 +323,10 @@ int ltrk_tune_cache_load(const char* path) {
                     &p.turns_per_launch, &p.block, &p.ppl, &p.use_graph) == 9 &&
         plan_valid(p) && valid_integrator(integ) && valid_dtype(dtype)) {
       g_tuned[TuneKey(arch, integ, dtype, bucket, batched)] = p;
-      ++loaded;
     }
   }
   std::fclose(f);
-  return loaded >= 0 ? LTRK_OK : LTRK_EINVAL;
+  return LTRK_OK;
 }
 
 }  // extern "C"
