@@ -9,10 +9,10 @@
 //                    previous turn's potential, adds the moment sums of that
 //                    turn, runs one step of the map and bins z into the
 //                    block's LDS slice histogram, then adds the non-zero bins
-//                    into the global slice counts (integer adds, so the
-//                    counts do not depend on the order of the blocks);
-//   k_wake_potential one block reads the counts into LDS (and zeroes them
-//                    for the next turn) and forms the causal potential
+//                    into its copy of the global slice counts (integer adds,
+//                    so the counts do not depend on the order of the blocks);
+//   k_wake_potential one block adds the copies of the counts into LDS (and
+//                    zeroes them for the next turn) and forms the causal potential
 //                    V_k = sum_{j >= k} count_j W_{j-k}, each sum split into
 //                    up to 4 consecutive j ranges added in range order.
 // k_wake_turn runs a grid-stride loop over wave tiles on a fixed grid, so a
@@ -134,15 +134,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c
     // start each block at its own slice so that blocks finishing together
     // add into different counters
     const int rot = static_cast<int>((static_cast<int64_t>(blockIdx.x) * 61) % w.n_slices);
+    uint32_t* counts =
+        w.counts + (blockIdx.x % kWakeCountCopies) * kWakeCountStride(w.n_slices);
     for (int i = tid; i < w.n_slices; i += blockDim.x) {
       const int k = i + rot < w.n_slices ? i + rot : i + rot - w.n_slices;
-      if (hist[k] != 0u) atomicAdd(&w.counts[k], hist[k]);
+      if (hist[k] != 0u) atomicAdd(&counts[k], hist[k]);
     }
   }
 }
 
 // The causal potential V_k = sum_{j >= k} count_j W_{j-k} from the slice
-// counts (staged in LDS), which are then zeroed for the next turn; one block.
+// counts (the copies added and staged in LDS), which are then zeroed for the
+// next turn; one block.
 // The sum of slice k is split into `parts` consecutive j ranges added by
 // neighbouring threads, whose partial sums are then added in range order.
 // The wake table is staged in LDS when it fits beside the counts.
@@ -153,9 +156,15 @@ __global__ __launch_bounds__(kWakePotThreads) void k_wake_potential(WakeDev w) {
   double* cnt = sh;                           // n_slices
   double* part = sh + ns;                     // kWakePotThreads
   double* wl = part + kWakePotThreads;        // n_slices when staged
+  const int stride = kWakeCountStride(ns);
   for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-    cnt[k] = static_cast<double>(w.counts[k]);
-    w.counts[k] = 0u;
+    uint64_t total = 0;
+#pragma unroll
+    for (int c = 0; c < kWakeCountCopies; ++c) {
+      total += w.counts[c * stride + k];
+      w.counts[c * stride + k] = 0u;
+    }
+    cnt[k] = static_cast<double>(total);
     if (stage_w) wl[k] = w.wtab[k];
   }
   __syncthreads();
@@ -247,8 +256,8 @@ hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s) {
 
 hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s) {
   if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_wake_zero, dim3((w.n_slices + 255) / 256), dim3(256), 0, s, w.counts,
-                     w.n_slices);
+  const int n = kWakeCountCopies * kWakeCountStride(w.n_slices);
+  hipLaunchKernelGGL(k_wake_zero, dim3((n + 255) / 256), dim3(256), 0, s, w.counts, n);
   return hipGetLastError();
 }
 

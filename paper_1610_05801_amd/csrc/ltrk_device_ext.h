@@ -81,13 +81,18 @@ constexpr int kWakeMaxSlices = 4096;
 constexpr int kWakeMaxBlocks = 1024;
 constexpr int kWakePotThreads = 1024;   // block of the potential kernel
 constexpr int kWakeStageSlices = 2048;  // wake table staged in LDS up to this many slices
+// The global slice counts are held in kWakeCountCopies copies, kWakeCountStride(n)
+// counters apart; block b adds into copy b % kWakeCountCopies, which spreads
+// the blocks' end-of-turn atomic adds over eight addresses per slice.
+constexpr int kWakeCountCopies = 8;
+__host__ __device__ constexpr int kWakeCountStride(int n_slices) { return (n_slices + 63) & ~63; }
 
 struct WakeDev {
   double z_lo;
   double dz;
   double kappa;          // q Q_mp / (beta p0 c): delta kick per volt of potential
   const double* wtab;    // [n_slices] W(m dz / (beta c)), W(0) half the limit
-  uint32_t* counts;      // [n_slices] counts of the last map step (zero between turns)
+  uint32_t* counts;      // [kWakeCountCopies][stride] counts of the last map step (zero between turns)
   double* pot;           // [n_slices] potential of the last counts
   int32_t n_slices;
   int32_t pad;

@@ -1217,7 +1217,8 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)gwaves);
   }
   const size_t part_bytes = mom ? static_cast<size_t>(rows) * 5 * cols * sizeof(double) : 0;
-  const size_t hist_bytes = (static_cast<size_t>(ns) * sizeof(uint32_t) + 255) & ~size_t(255);
+  const size_t hist_bytes = static_cast<size_t>(kWakeCountCopies) * kWakeCountStride(ns) *
+                            sizeof(uint32_t);  // a multiple of 256 B
   const size_t pot_bytes = static_cast<size_t>(ns) * sizeof(double);
   void* scratch = nullptr;
   if ((rc = ensure_scratch(c, s, part_bytes + hist_bytes + pot_bytes, &scratch))) return rc;
