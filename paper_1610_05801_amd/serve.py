@@ -67,6 +67,11 @@ def run_stream(engine: Engine, requests, k: int = 256, keep_results: bool = Fals
                 break
             waiting.popleft()
             active[slot] = (r, clock() - t0)
+        if waiting and not active:
+            # nothing of this loop runs that could free a slot or space
+            raise RuntimeError("request %d does not fit into the engine although none of this "
+                               "loop's jobs are running (slots or space held elsewhere)"
+                               % waiting[0].rid)
         if active:
             advanced = engine.step(k)
             progressed = False

@@ -107,3 +107,16 @@ def test_job_that_never_fits_raises():
     eng = FakeEngine(budget=1024, slots=2)
     with pytest.raises(binding.LtrkError):
         serve.run_stream(eng, reqs, k=10)
+
+
+def test_request_refused_by_an_idle_engine_raises():
+    """A slot held outside the loop and no job of the loop running: nothing
+    would ever free room for the request, so the loop raises instead of
+    waiting forever."""
+    eng = FakeEngine(budget=10 * FakeEngine.footprint(400, 120), slots=1)
+    z0, dp0 = gaussian_bunch(10, 0.2, 1e-3, 2)
+    eng.admit(10, 10, SPS_RING, "leapfrog", "f64", z0, dp0)      # held by someone else
+    reqs = [serve.Request(0, 0.0, 10, 10, SPS_RING, "leapfrog", "f64", (z0, dp0))]
+    with pytest.raises(RuntimeError):
+        serve.run_stream(eng, reqs, k=10)
+
