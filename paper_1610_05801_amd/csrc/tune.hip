@@ -44,12 +44,19 @@ bool plan_valid(const ltrk_plan& p) {
   return k_ok && b_ok && p_ok && (p.use_graph == 0 || p.use_graph == 1);
 }
 
+// Architecture name of the current device (cached per device: the property
+// query costs more than the rest of a call's host work).
 std::string device_arch() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return "unknown";
   }
+  static std::mutex mu;
+  static std::map<int, std::string> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
     (void)hipGetLastError();
@@ -57,7 +64,9 @@ std::string device_arch() {
   }
   std::string a(prop.gcnArchName);
   const size_t colon = a.find(':');
-  return colon == std::string::npos ? a : a.substr(0, colon);
+  a = colon == std::string::npos ? a : a.substr(0, colon);
+  cache[dev] = a;
+  return a;
 }
 
 int log2_bucket(int64_t n) {
