@@ -124,6 +124,28 @@ def test_strerror_and_plans():
     assert ltrk.ltrk_get_plan("leapfrog", "f64", 1_000_000) == p
 
 
+def test_tune_cache_file_roundtrip(tmp_path):
+    """Loading a tuning-cache file merges its valid entries (written here for
+    this host's architecture name, gfx950 or "unknown" without a GPU) and
+    skips comments, malformed lines and invalid plans; saving writes the
+    entries back; a missing file is an error."""
+    ltrk.ltrk_set_plan()
+    src = tmp_path / "in.txt"
+    src.write_text("# arch integrator dtype log2n batched K block ppl graph\n"
+                   "not a plan line\n"
+                   "unknown 3 1 1 0 48 64 2 0\n"
+                   "gfx950 3 1 1 0 48 64 2 0\n"
+                   "gfx950 3 1 1 0 48 96 2 0\n")      # block 96: invalid, skipped
+    ltrk.ltrk_tune_cache_load(str(src))
+    assert ltrk.ltrk_get_plan("rk4", "f32c", 3) == {"turns_per_launch": 48, "block": 64,
+                                                    "ppl": 2, "use_graph": 0}
+    out = tmp_path / "out.txt"
+    ltrk.ltrk_tune_cache_save(str(out))
+    assert "3 1 1 0 48 64 2 0" in out.read_text()
+    with pytest.raises(ltrk.LtrkError):
+        ltrk.ltrk_tune_cache_load(str(tmp_path / "missing.txt"))
+
+
 def test_engine_footprint():
     assert ltrk.ltrk_engine_footprint(1000, 100) == 16128 + 4096
     assert ltrk.ltrk_engine_footprint(10_000_000, 100_000) == 160_000_000 + 4_000_000
