@@ -31,6 +31,12 @@
  *     the ABI.
  *   - n = 0 or turns = 0 is a successful no-op, except that with n = 0 and
  *     turns > 0 the moment rows (if requested) are filled with NaN.
+ *   - A caller may capture a call into a graph of its own (stream capture):
+ *     the call then enqueues its kernels into the capture instead of
+ *     replaying a cached graph. Run the same call once on that stream before
+ *     capturing, so that its scratch exists and the captured call allocates
+ *     nothing. The programme and wake entry points refuse capture
+ *     (EUNSUPPORTED: they upload a table).
  */
 #ifndef LTRK_H
 #define LTRK_H

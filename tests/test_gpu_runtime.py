@@ -167,6 +167,44 @@ def test_long_sequences_run_eagerly_in_pieces(ltrk, monkeypatch):
         assert np.isfinite(a).all() and np.array_equal(a, b)
 
 
+def test_calls_captured_by_the_caller_replay_exactly(ltrk):
+    """A caller may capture a call into a graph of its own (here torch's, on a
+    stream that one eager call has already set up, so the captured call
+    allocates nothing): the library enqueues its kernels into the capture, and
+    every replay, with the state restored by the program between replays,
+    equals the eager call bit for bit."""
+    z0, dp0 = gaussian_bunch(50_000, 0.2, 1e-3, 21)
+    T = 96
+    s = torch.cuda.Stream()
+    ltrk.ltrk_set_plan(16, 256, 4, 1)
+    try:
+        z_init, d_init = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+        z, dp = z_init.clone(), d_init.clone()
+        mom = torch.empty((T, 5), dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(s):
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom, stream=s)
+        s.synchronize()
+        ze, de, me = z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy()
+        z.copy_(z_init)
+        dp.copy_(d_init)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", mom, stream=s)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            z.copy_(z_init)
+            dp.copy_(d_init)
+            mom.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(z.cpu().numpy(), ze) and np.array_equal(dp.cpu().numpy(), de)
+            assert np.array_equal(mom.cpu().numpy(), me)
+    finally:
+        ltrk.ltrk_set_plan()
+
+
 def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
     n = 200_000
     best = ltrk.ltrk_autotune("leapfrog", "f64", n)
