@@ -21,7 +21,9 @@ bunches), serving (Poisson request stream through the engine), ksweep,
 schemes (every integrator), rf2 (double-harmonic RF, slip factor to second
 order in dp), program (per-turn RF settings and a momentum ramp), 6d
 (transverse linear map with chromaticity plus the longitudinal step), wake
-(longitudinal resonator wake kick every turn).
+(longitudinal resonator wake kick every turn), nsweep (the paper's
+small-n table: 1 ... 8192 and up to 1e6 particles against the single-core
+oracle, S and S_pure).
 """
 from __future__ import annotations
 
@@ -131,11 +133,23 @@ def _oracle_rate(z0, dp0, turns_total, ring, threads, budget_s):
     return z0.size * turns / dt, turns, dt
 
 
+def host_cpu_model() -> str:
+    """The CPU model name from /proc/cpuinfo (the machine type where there is none)."""
+    import platform
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
     """The FP64 oracle on the host cores: a bounded sample of the workload
     (the same bunch, its first T turns), scaled to particle-turns/s; also on
     one core (a tenth of the bunch, a third of the budget)."""
-    import platform
     from synth import SIGMA_DP, SIGMA_Z, gaussian_bunch
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
     threads = len(os.sched_getaffinity(0))
@@ -149,7 +163,8 @@ def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
             "single_core": {"value": rate1, "ns_per_particle_turn": 1e9 / rate1,
                             "sample": "%d particles x first %d turns on 1 thread, %.1f s wall"
                                       % (n1, turns1, dt1)},
-            "host_cpu": platform.processor() or platform.machine()}
+            "host_cpu": host_cpu_model(), "nproc": os.cpu_count(),
+            "threads_available": threads}
 
 
 TIMING_STEPS = 5   # steps replayed with launch timing on, for the per-launch kernel times
@@ -163,9 +178,21 @@ def bench_default(args):
     n, T = args.particles, args.turns
     integ = "leapfrog"
     seed = SEEDS["paper_scale"]
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream(device=dev)
     log("bench: %d particles x %d turns, %s FP64" % (n, T, integ))
+    # Stages outside the rate, as the paper's stage profile lists them
+    # (host timers around device-synchronised stages): device init, device
+    # allocation, host-to-device copy of the initial state, the first call
+    # (scratch allocation and launch-graph build), one tracking step (the
+    # median of the timed steps), device-to-host copy of the final state and
+    # the moment rows, and freeing the device memory.
+    stages = {}
+    t0 = time.perf_counter()
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    torch.empty(1, device=dev)
+    torch.cuda.synchronize()
+    stages["init"] = (time.perf_counter() - t0) * 1e3
+    stream = torch.cuda.Stream(device=dev)
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, seed)
     zt, dt = torch.as_tensor(z0), torch.as_tensor(dp0)
     if args.tune:
@@ -179,11 +206,18 @@ def bench_default(args):
     # timed steps; the per-launch kernel times come from TIMING_STEPS more
     # steps with timing on (a second, timed graph: event-record nodes between
     # its segments), after one step that builds that graph.
-    z_init, d_init = zt.to(dev), dt.to(dev)
+    t0 = time.perf_counter()
+    z_init, d_init = torch.empty(n, dtype=torch.float64, device=dev), torch.empty_like(zt, device=dev)
     z_run, d_run = torch.empty_like(z_init), torch.empty_like(d_init)
     mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
-    moms = [mom]
     torch.cuda.synchronize()
+    stages["alloc"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    z_init.copy_(zt)
+    d_init.copy_(dt)
+    torch.cuda.synchronize()
+    stages["h2d"] = (time.perf_counter() - t0) * 1e3
+    moms = [mom]
 
     def restore():
         z_run.copy_(z_init)
@@ -194,7 +228,11 @@ def bench_default(args):
         ltrk.ltrk_timing_enable(False)
         for i in range(args.warmup):
             restore()
+            t0 = time.perf_counter()
             ltrk.ltrk_track_f64(z_run, d_run, T, SPS_RING, integ, mom, stream=stream)
+            if i == 0:
+                stream.synchronize()
+                stages["first_call"] = (time.perf_counter() - t0) * 1e3
         stream.synchronize()
         step_ms = []
         for i in range(args.steps):
@@ -249,6 +287,7 @@ def bench_default(args):
                 if r:
                     f32_s += (time.perf_counter() - t0) / reps
         v32 = n * T / f32_s
+        del f32, f32_run
         extras["f32c"] = {"value": v32, "unit": "particle-turns/s", "ms_per_step": f32_s * 1e3,
                           "ratio_to_f64": v32 / value}
         log("f32c: %.4e particle-turns/s" % v32)
@@ -271,7 +310,23 @@ def bench_default(args):
                              "turns": Tu, "note": "16 MB state is cache resident at 1e6 "
                              "particles; the HBM roofline sweep is --workload unfused"}
         log("unfused: %.4e particle-turns/s" % (n * Tu / du))
-        del saved
+        del saved, z1, d1, mu
+        extras["unfused_hbm"] = unfused_hbm_leg(ltrk, torch, stream, dev)
+
+    # final state and moment rows to the host, then free the device memory
+    t0 = time.perf_counter()
+    host_out = (z_run.cpu(), d_run.cpu(), mom.cpu())
+    torch.cuda.synchronize()
+    stages["d2h"] = (time.perf_counter() - t0) * 1e3
+    del host_out
+    t0 = time.perf_counter()
+    del z_init, d_init, z_run, d_run, mom, moms
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    stages["free"] = (time.perf_counter() - t0) * 1e3
+    stages["track"] = percentile(step_ms, 50)
+    pcie = stages["h2d"] + stages["track"] + stages["d2h"]
 
     out = {
         "metric": METRIC,
@@ -293,6 +348,12 @@ def bench_default(args):
         "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99),
                        "unit": "ms per step (1e10 particle-turns)"},
         "roofline": roofline,
+        "stages_ms": dict(stages, note="host timers around device-synchronised stages; "
+                          "track = median step; first_call = the first call's scratch "
+                          "allocation, graph build and run"),
+        "pcie_inclusive": {"value": n * T / (pcie * 1e-3), "unit": "particle-turns/s",
+                           "note": "one step with the initial state copied in and the final "
+                                   "state and moments copied out (h2d + track + d2h)"},
     }
     out.update(extras)
     if not args.no_cpu:
@@ -304,6 +365,41 @@ def bench_default(args):
         log("cpu: %.4e particle-turns/s on %d threads, %.4e on one" % (
             cb["value"], cb["cores"], cb["single_core"]["value"]))
     print(json.dumps(out), flush=True)
+
+
+# The HBM-bound form at a size far beyond the 256 MB last-level cache:
+# one launch per turn, 2 particles per lane in 64-thread blocks (the fastest
+# shape of the --workload unfused sweep at 1e8 particles).
+UNFUSED_HBM_N, UNFUSED_HBM_TURNS = 100_000_000, 30
+
+
+def unfused_hbm_leg(ltrk, torch, stream, dev):
+    """One launch per turn at 1e8 particles (1.6 GB of state): kernel time per
+    launch from HIP events, algorithmic bytes 32 per particle-turn."""
+    n, turns = UNFUSED_HBM_N, UNFUSED_HBM_TURNS
+    g = torch.Generator(device=dev).manual_seed(7)
+    z = torch.randn(n, dtype=torch.float64, device=dev, generator=g) * 0.23
+    dp = torch.randn(n, dtype=torch.float64, device=dev, generator=g) * 1e-3
+    mom = torch.empty((turns, 5), dtype=torch.float64, device=dev)
+    ltrk.ltrk_set_plan(1, 64, 2, 1)
+    reps = 3
+    try:
+        dt, tm = _timed_track(ltrk, torch, stream, n, turns, "leapfrog", "f64", (z, dp), mom,
+                              reps=reps)
+    finally:
+        ltrk.ltrk_set_plan()
+    kern_ms = tm["track_ms"] / max(tm["track_launches"], 1)
+    achieved = STATE_BYTES_PER_PARTICLE * 2 * n / (kern_ms * 1e-3) / 1e9
+    del z, dp, mom
+    torch.cuda.empty_cache()
+    leg = {"bound": "hbm", "particles": n, "turns": turns, "plan": {"turns_per_launch": 1,
+           "block": 64, "ppl": 2}, "avg_launch_ms": kern_ms, "achieved": achieved,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "bytes_per_particle_turn": 2 * STATE_BYTES_PER_PARTICLE,
+           "particle_turns_per_s": n * turns / dt,
+           "finalize_ms_per_turn": tm["finalize_ms"] / (reps * turns)}
+    log("unfused at 1e8: %.0f GB/s (%.3f of HBM peak)" % (achieved, achieved / HBM_PEAK_GBS))
+    return leg
 
 
 def _timed_track(ltrk, torch, stream, n, turns, integ, dtype, arrays, mom, reps=1):
@@ -388,6 +484,70 @@ def bench_unfused(args):
     ltrk.ltrk_set_plan()
     print(json.dumps({"workload": "unfused leap-frog FP64, one launch per turn", "rows": rows,
                       "bytes_per_particle_turn": 32, "peak_GBps": HBM_PEAK_GBS}), flush=True)
+
+
+NSWEEP_N = tuple(2 ** k for k in range(14)) + (10_000, 100_000, 1_000_000)
+
+
+def bench_nsweep(args):
+    """The paper's small-n table (Table 2: leap-frog, 1e6 turns, 1 ... 8192
+    macro-particles, sequential C against the GPU, S and S_pure), extended to
+    1e6 particles. Per n: the GPU call's kernel time (HIP events over its
+    tracking launches) and its total (host copy in, the call, copy out; warm
+    process), the single-core oracle's time (measured on the first turns and
+    scaled to all turns: its cost per turn is constant), S = oracle / GPU
+    total, S_pure = oracle / GPU kernel (the oracle reads no files, so its
+    total and kernel times are one number), the break-even n and the
+    single-particle per-turn latency. No moments, as in the paper's kernels."""
+    import torch
+    import oracle
+    import paper_1610_05801_amd as ltrk
+    from synth import SIGMA_DP, SIGMA_Z, SPS_RING, SEEDS, gaussian_bunch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    T = args.sweep_turns
+    rows = []
+    oracle_budget_pt = 2.5e7   # about 0.3 s of single-core oracle work per row
+    for n in NSWEEP_N:
+        z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
+        z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+        with torch.cuda.stream(stream):
+            ltrk.ltrk_timing_enable(True)
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", None, stream=stream)
+            stream.synchronize()          # the first call builds the launch graph
+            ltrk.ltrk_timing_take()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+            ltrk.ltrk_track_f64(z, dp, T, SPS_RING, "leapfrog", None, stream=stream)
+            out = (z.cpu(), dp.cpu())
+            torch.cuda.synchronize()
+            total_ms = (time.perf_counter() - t0) * 1e3
+            tm = ltrk.ltrk_timing_take()
+            ltrk.ltrk_timing_enable(False)
+        del out
+        kern_ms = tm["track_ms"]
+        t_or = int(min(T, max(100, oracle_budget_pt / n)))
+        t0 = time.perf_counter()
+        oracle.track(z0, dp0, t_or, SPS_RING, "leapfrog", with_moments=False, threads=1)
+        or_ms = (time.perf_counter() - t0) * 1e3 * T / t_or
+        row = {"particles": n, "turns": T, "gpu_kernel_ms": kern_ms, "gpu_total_ms": total_ms,
+               "launches": tm["track_launches"], "oracle_1core_ms": or_ms,
+               "oracle_turns_measured": t_or, "S": or_ms / total_ms, "S_pure": or_ms / kern_ms,
+               "gpu_particle_turns_per_s": n * T / (kern_ms * 1e-3)}
+        rows.append(row)
+        log(json.dumps(row))
+        del z, dp
+    even = [r["particles"] for r in rows if r["S"] >= 1.0]
+    out = {"workload": "nsweep: leap-frog FP64, %d turns, no moments, 1 ... 1e6 particles" % T,
+           "rows": rows, "break_even_particles": even[0] if even else None,
+           "break_even_particles_pure": next((r["particles"] for r in rows if r["S_pure"] >= 1.0),
+                                             None),
+           "single_particle_ns_per_turn": rows[0]["gpu_kernel_ms"] * 1e6 / T,
+           "oracle_cpu": host_cpu_model(),
+           "note": "GPU totals are warm-process calls (device init excluded: see the default "
+                   "run's stages_ms); oracle times scaled from oracle_turns_measured turns"}
+    print(json.dumps(out), flush=True)
 
 
 def bench_ksweep(args):
@@ -1097,9 +1257,11 @@ def main():
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "unfused", "precision", "batched", "serving", "ksweep",
                              "counters", "counters_f32c", "schemes", "rf2", "program", "6d",
-                             "wake", "latency"])
+                             "wake", "latency", "nsweep"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
+    ap.add_argument("--sweep-turns", type=int, default=1_000_000,
+                    help="turns of every row of --workload nsweep (the paper's table: 1e6)")
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
     ap.add_argument("--quick", action="store_true", help="skip the FP32 and unfused legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -1125,7 +1287,8 @@ def main():
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,
      "counters": bench_counters, "schemes": bench_schemes,
      "rf2": bench_rf2, "program": bench_program, "6d": bench_6d, "wake": bench_wake,
-     "latency": bench_latency, "counters_f32c": bench_counters_f32c}[args.workload](args)
+     "latency": bench_latency, "counters_f32c": bench_counters_f32c,
+     "nsweep": bench_nsweep}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -35,8 +35,12 @@
  *     the call then enqueues its kernels into the capture instead of
  *     replaying a cached graph. Run the same call once on that stream before
  *     capturing, so that its scratch exists and the captured call allocates
- *     nothing. The programme and wake entry points refuse capture
- *     (EUNSUPPORTED: they upload a table).
+ *     nothing: a captured call that would need more moment-partial scratch
+ *     than its stream has returns EUNSUPPORTED before enqueueing anything.
+ *     When an uncaptured call grows a stream's scratch, the old buffer stays
+ *     allocated until ltrk_shutdown, so graphs captured before stay valid.
+ *     The programme, wake and batched entry points refuse capture
+ *     (EUNSUPPORTED: they upload tables).
  */
 #ifndef LTRK_H
 #define LTRK_H
@@ -287,7 +291,9 @@ typedef struct ltrk_bunch {
  * state precision: each launch sweeps a tile table covering every bunch, so
  * all bunches move together. `bunches` is a HOST array of nb descriptors;
  * the arrays it names are device memory. Results per bunch are those of
- * ltrk_track_f64/f32c on that bunch with the same plan. */
+ * ltrk_track_f64/f32c on that bunch with the same plan. EUNSUPPORTED, before
+ * anything is enqueued, for a stream that is being captured into a graph (the
+ * bunch and tile tables are uploaded per call). */
 int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int integrator,
                        int dtype, void* stream);
 

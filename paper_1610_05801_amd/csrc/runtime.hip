@@ -601,6 +601,16 @@ hipError_t build_timed_graph(const std::vector<Launch>& seq, hipStream_t s, Grap
   return hipSuccess;
 }
 
+bool stream_capturing(hipStream_t s) {
+  if (!s) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
 struct Scratch {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -620,6 +630,7 @@ struct ProgBuf {
 struct DeviceCtx {
   std::mutex mu;
   std::unordered_map<hipStream_t, Scratch> scratch;
+  std::vector<void*> retired;  // grown-out scratch buffers, freed at shutdown
   std::unordered_map<hipStream_t, ProgBuf> progs;
   std::list<std::pair<std::string, GraphEntry>> graphs;  // most recent first
   size_t max_graphs = 32;
@@ -670,26 +681,38 @@ void clear_graphs(DeviceCtx& c) {
   c.graphs.clear();
 }
 
-// Scratch of at least `bytes` for stream s (grown, never shrunk).
+// Scratch of at least `bytes` for stream s (grown, never shrunk). A grown-out
+// buffer is kept until shutdown rather than freed: graphs that a caller
+// captured from earlier calls on the stream still name it (cached graphs of
+// the library key on the scratch address, so they keep using it too). Growth
+// at least doubles the buffer, so the kept buffers add up to less than the
+// current one. Under stream capture the scratch cannot grow (EUNSUPPORTED).
 int ensure_scratch(DeviceCtx& c, hipStream_t s, size_t bytes, void** out) {
   Scratch& sc = c.scratch[s];
   if (sc.bytes >= bytes && sc.ptr) {
     *out = sc.ptr;
     return LTRK_OK;
   }
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize before scratch growth");
-  clear_graphs(c);  // cached graphs may name the old buffer
-  if (sc.ptr) hipFree(sc.ptr);
-  sc.ptr = nullptr;
-  sc.bytes = 0;
+  if (stream_capturing(s))
+    return fail(LTRK_EUNSUPPORTED,
+                "the call needs %zu bytes of scratch on a capturing stream that has %zu; run it "
+                "once uncaptured first",
+                bytes, sc.bytes);
   size_t want = std::max(bytes, static_cast<size_t>(1) << 20);
-  e = hipMalloc(&sc.ptr, want);
+  if (sc.ptr) want = std::max(want, 2 * sc.bytes);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess && want > bytes) {  // the doubling alone may not fit
+    (void)hipGetLastError();
+    want = std::max(bytes, static_cast<size_t>(1) << 20);
+    e = hipMalloc(&p, want);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    sc.ptr = nullptr;
     return fail(LTRK_ENOMEM, "scratch allocation of %zu bytes failed", want);
   }
+  if (sc.ptr) c.retired.push_back(sc.ptr);
+  sc.ptr = p;
   sc.bytes = want;
   *out = sc.ptr;
   return LTRK_OK;
@@ -749,15 +772,6 @@ int send_program(DeviceCtx& c, hipStream_t s, size_t bytes) {
   return LTRK_OK;
 }
 
-bool stream_capturing(hipStream_t s) {
-  if (!s) return false;
-  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return st != hipStreamCaptureStatusNone;
-}
 
 // Run `seq` on s: from the graph cache under `key` when allowed, else eagerly.
 // `owned` device tables are kept alive with the cached graph (or freed after
@@ -1377,6 +1391,9 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
     total_n += b.n;
   }
   if (turns == 0 || nb == 0) return LTRK_OK;
+  if (stream_capturing(s))
+    return fail(LTRK_EUNSUPPORTED,
+                "a batched call cannot be captured: it uploads its bunch and tile tables");
   for (int i = 0; i < nb; ++i) {
     if (bunches[i].n == 0 && bunches[i].moments) {
       hipError_t e = launch_fill_nan(bunches[i].moments, turns, s);
@@ -1465,7 +1482,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
 
   // Device tables: found with a cached graph, else uploaded now.
   const int64_t expected = count_launches(turns, rows, K, fin.empty() ? 0 : 1);
-  const bool graph_ok = plan.use_graph && s && !stream_capturing(s) &&
+  const bool graph_ok = plan.use_graph && s &&
                         expected <= static_cast<int64_t>(max_graph_launches());
   if (graph_ok) {
     const std::string gkey = graph_key(key);
@@ -1561,6 +1578,8 @@ static int shutdown_all() {
     for (auto& sc : c.scratch)
       if (sc.second.ptr) hipFree(sc.second.ptr);
     c.scratch.clear();
+    for (void* r : c.retired) hipFree(r);
+    c.retired.clear();
     for (auto& pg : c.progs) {
       if (pg.second.dev) hipFree(pg.second.dev);
       if (pg.second.host) hipHostFree(pg.second.host);

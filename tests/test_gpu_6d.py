@@ -2,8 +2,11 @@
 the extended longitudinal step) through the C ABI, against the oracle's 6-D
 map and against exact matrix powers.
 
-Longitudinal per-particle tolerance as for the extended map (8 u turns times
-the oracle-measured sensitivity). Transverse: the error in the
+Longitudinal per-particle bounds as for the single-harmonic map
+(tests/_parity.py: check_particles: 1e-12 after 1e3 turns, in proportion
+beyond; a particle over it held to 8 ulp per turn times its oracle-measured
+sensitivity, capped at 1e-10 after 1e3 turns; at most 0.5% over 1e-12; the
+(z, dp) part of the 6-D map is the extended map alone). Transverse: the error in the
 Courant-Snyder amplitude sqrt(beta J) stays below 1e-12 after 1e3 turns (it
 comes from the phase of each turn, ~1e-16 per turn; chromaticity carries the
 longitudinal differences in over 2 pi Q' delta, below that)."""
@@ -15,7 +18,7 @@ import pytest
 
 import oracle
 from synth import SPS_RING, gaussian_bunch
-from tests._parity import moment_error
+from tests._parity import amplification, check_particles, moment_error
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,14 +73,13 @@ def trans_err(out, ref, plane):
     return np.hypot(out[u] - ref[u], b * (out[v] - ref[v])) / amp
 
 
-def long_tolerance(st, turns, integ):
-    eps = 1e-13
+def long_check(el, st, turns, integ, label):
     kw = dict(with_moments=False, threads=1 if len(st["z"]) < 2000 else 0)
-    za, da, _ = oracle.track_rf2(st["z"], st["dp"], turns, RF, integ, **kw)
-    zb, db, _ = oracle.track_rf2(st["z"] * (1 + eps), st["dp"], turns, RF, integ, **kw)
-    zc, dc, _ = oracle.track_rf2(st["z"], st["dp"] * (1 + eps), turns, RF, integ, **kw)
-    amp = np.maximum(long_err(zb, db, za, da), long_err(zc, dc, za, da)) / eps
-    return 8 * 2.0 ** -53 * turns * np.maximum(amp, 1.0)
+    return check_particles(
+        el, np.zeros(el.size, dtype=bool), turns,
+        lambda m: amplification(oracle.track_rf2, st["z"][m], st["dp"][m], turns, RF, integ,
+                                err=long_err, **kw),
+        label=label)
 
 
 @pytest.mark.parametrize("integ", ["euler_cromer", "leapfrog", "ruth4", "rk4"])
@@ -86,7 +88,7 @@ def test_6d_against_oracle(ltrk, integ):
     out, mom = run(ltrk, st, 1000, integ)
     ref, mr = oracle.track_6d(st, 1000, RF, TW, integ)
     el = long_err(out["z"], out["dp"], ref["z"], ref["dp"])
-    assert np.all(el <= long_tolerance(st, 1000, integ))
+    long_check(el, st, 1000, integ, "6-D longitudinal %s" % integ)
     ex, ey = trans_err(out, ref, "x"), trans_err(out, ref, "y")
     print("%s 6-D: long e max %.2e, x e max %.2e, y e max %.2e" % (integ, el.max(), ex.max(),
                                                                    ey.max()))
@@ -153,7 +155,7 @@ def test_6d_paper_scale_sampled(ltrk):
     ref, _ = oracle.track_6d(sub, T, RF, TW, "leapfrog", with_moments=False, threads=1)
     got = {k: out[k][idx] for k in KEYS}
     el = long_err(got["z"], got["dp"], ref["z"], ref["dp"])
-    assert np.all(el <= long_tolerance(sub, T, "leapfrog"))
+    long_check(el, sub, T, "leapfrog", "6-D longitudinal 1e6 x 1e4 sample")
     ex, ey = trans_err(got, ref, "x"), trans_err(got, ref, "y")
     print("6-D paper scale: long e max %.2e, x e max %.2e, y e max %.2e" % (el.max(), ex.max(),
                                                                           ey.max()))

@@ -63,6 +63,8 @@ def test_batched_f64_matches_oracle_and_alone(ltrk, integ):
         near = near_separatrix(z0, dp0, r)
         if (~near).any():
             assert e[~near].max() <= 1e-12
+        if near.any():
+            assert e[near].max() <= 1e-10
         if s.n > 1:
             assert moment_error(mom, mr).max() <= 1e-10
         # alone, same plan: bitwise

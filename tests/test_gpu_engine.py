@@ -1,13 +1,17 @@
 """Serving engine: jobs of different sizes, schemes and precisions admitted
 while others run, advanced together step by step; each job's result is
-bitwise equal to tracking it alone with the same particles-per-lane (4), and
-admission respects slots and the arena budget."""
+bitwise equal to tracking it alone with the same particles-per-lane (8), the
+FP64 jobs' results also match the oracle directly (tests/_parity.py bounds),
+and admission respects slots and the arena budget."""
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 from synth import SPS_RING, gaussian_bunch, split_f32c
+from tests._parity import (amplification, bucket_error, check_particles, moment_error,
+                           near_separatrix)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -93,6 +97,15 @@ def test_engine_mix_equals_alone(ltrk):
             pairs = list(zip(got, ref))
         for a, b in pairs:
             assert np.array_equal(a, b), (i, JOBS[i])
+        if dt == "f64":
+            # the job's result in the mix against the oracle itself
+            zr, dr, mr = oracle.track(z0, dp0, T, SPS_RING, integ)
+            e = bucket_error(got[0], got[1], zr, dr, SPS_RING)
+            check_particles(e, near_separatrix(z0, dp0, SPS_RING), T,
+                            lambda m: amplification(oracle.track, z0[m], dp0[m], T, SPS_RING,
+                                                    integ),
+                            label="engine job %d %s" % (i, integ))
+            assert moment_error(got[2], mr).max() <= 1e-10
     st = eng.stats()
     assert st["active_slots"] == 0 and st["arena_free_bytes"] == st["arena_bytes"]
     eng.close()

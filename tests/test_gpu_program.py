@@ -3,9 +3,13 @@ through the C ABI, against the oracle's programme map; a constant programme
 against the extended-map kernel bit for bit; launch-plan and call-split
 invariance.
 
-Per-particle tolerance as for the extended map: e_i <= 8 u turns max(amp_i, 1)
-with amp_i the particle's sensitivity measured with the oracle (relative
-perturbations of 1e-13 in z and in dp)."""
+Per-particle bounds as for the single-harmonic map (tests/_parity.py:
+check_particles): e <= 1e-12 after 1e3 turns (in proportion beyond); a
+particle over it is held to 8 ulp per turn times its sensitivity measured
+with the oracle (relative perturbations of 1e-13 in z and in dp), capped at
+1e-10 after 1e3 turns, and at most 0.5% of the bunch may be over 1e-12. The
+bunches stay inside their buckets, so none is counted as near the
+separatrix."""
 import math
 
 import numpy as np
@@ -13,7 +17,7 @@ import pytest
 
 import oracle
 from synth import SPS_RING, gaussian_bunch
-from tests._parity import moment_error
+from tests._parity import amplification, check_particles, moment_error
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,14 +61,15 @@ def err(z, dp, zr, dr):
     return np.hypot((z - zr) / zb, (dp - dr) / db) / np.hypot(zr / zb, dr / db)
 
 
-def tolerance(z0, dp0, turns, prog, integ):
-    eps = 1e-13
+def check(e, z0, dp0, turns, prog, integ, label):
     kw = dict(with_moments=False, threads=1 if len(z0) < 2000 else 0)
-    za, da, _ = oracle.track_program(z0, dp0, turns, RF, prog, integ, **kw)
-    zb, db, _ = oracle.track_program(z0 * (1 + eps), dp0, turns, RF, prog, integ, **kw)
-    zc, dc, _ = oracle.track_program(z0, dp0 * (1 + eps), turns, RF, prog, integ, **kw)
-    amp = np.maximum(err(zb, db, za, da), err(zc, dc, za, da)) / eps
-    return 8 * 2.0 ** -53 * turns * np.maximum(amp, 1.0), amp
+
+    def track(z, dp, t, rf, ig, **k):
+        return oracle.track_program(z, dp, t, rf, prog, ig, **k)
+    return check_particles(
+        e, np.zeros(e.size, dtype=bool), turns,
+        lambda m: amplification(track, z0[m], dp0[m], turns, RF, integ, err=err, **kw),
+        label=label)
 
 
 @pytest.fixture(scope="module")
@@ -94,12 +99,7 @@ def test_programme_against_oracle(ltrk, integ):
     z, dp, mom = run(ltrk, z0, dp0, turns, prog, integ)
     zr, dr, mr = oracle.track_program(z0, dp0, turns, RF, prog, integ)
     e = err(z, dp, zr, dr)
-    tol, amp = tolerance(z0, dp0, turns, prog, integ)
-    assert amp.max() < 1e3
-    worst = np.argmax(e / tol)
-    assert np.all(e <= tol), (e[worst], tol[worst], amp[worst])
-    print("%s programme: e p50 %.2e max %.2e, max e/tol %.2f" % (integ, np.median(e), e.max(),
-                                                                 (e / tol).max()))
+    check(e, z0, dp0, turns, prog, integ, "programme %s" % integ)
     assert moment_error(mom, mr).max() <= 1e-10
 
 
@@ -181,8 +181,5 @@ def test_programme_paper_scale_sampled(ltrk):
     zr, dr, _ = oracle.track_program(z0[idx], dp0[idx], T, RF, prog, "leapfrog",
                                      with_moments=False, threads=1)
     e = err(z[idx], dp[idx], zr, dr)
-    tol, amp = tolerance(z0[idx], dp0[idx], T, prog, "leapfrog")
-    assert np.all(e <= tol), (e / tol).max()
-    print("programme paper scale: e p50 %.2e max %.2e, max e/tol %.2f, amp max %.1f"
-          % (np.median(e), e.max(), (e / tol).max(), amp.max()))
+    check(e, z0[idx], dp0[idx], T, prog, "leapfrog", "programme 1e6 x 1e4 sample")
     assert moment_error(mom[-1:], oracle.moments(z, dp)[None, :]).max() <= 1e-12

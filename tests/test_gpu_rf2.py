@@ -2,14 +2,14 @@
 eta0 + eta1 dp + eta2 dp^2) through the C ABI, against the oracle's extended
 map.
 
-Per-particle tolerance from the arithmetic: both sides commit a few units of
-rounding u = 2^-53 per turn (the sine polynomial against libm, fused against
-separate multiply-adds), and a difference made at some turn grows by at most
-the particle's own sensitivity by the end. That sensitivity is measured with
-the oracle alone (relative perturbations of 1e-13 in z and in dp, worst of the
-two), so the bound is e_i <= 8 u turns max(amp_i, 1). In both configurations
-below every particle stays inside its bucket and amp_i <= 65 after 1e3 turns.
-Moments: 1e-10 relative, as for the single-harmonic map."""
+Per-particle bounds as for the single-harmonic map (tests/_parity.py:
+check_particles): e <= 1e-12 after 1e3 turns (in proportion beyond); a
+particle over it is held to 8 ulp per turn times its own orbit's
+sensitivity, measured with the oracle alone (relative perturbations of 1e-13
+in z and in dp, worst of the two), capped at 1e-10 after 1e3 turns, and at
+most 0.5% of the bunch may be over 1e-12. In both configurations below every
+particle stays inside its bucket (amplification <= 65 after 1e3 turns), so
+none is counted as near the separatrix. Moments: 1e-10 relative."""
 import math
 
 import numpy as np
@@ -17,7 +17,8 @@ import pytest
 
 import oracle
 from synth import SPS_RING, gaussian_bunch
-from tests._parity import amplification, moment_error, rounding_tolerance
+from tests._parity import (amplification, amplified_cap, check_particles, moment_error,
+                           rounding_tolerance)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,14 +44,12 @@ def err(z, dp, zr, dr):
     return np.hypot((z - zr) / zb, (dp - dr) / db) / np.hypot(zr / zb, dr / db)
 
 
-def tolerance(z0, dp0, turns, rf, integ):
-    eps = 1e-13
+def check(e, z0, dp0, turns, rf, integ, label):
     kw = dict(with_moments=False, threads=1 if len(z0) < 2000 else 0)
-    za, da, _ = oracle.track_rf2(z0, dp0, turns, rf, integ, **kw)
-    zb, db, _ = oracle.track_rf2(z0 * (1 + eps), dp0, turns, rf, integ, **kw)
-    zc, dc, _ = oracle.track_rf2(z0, dp0 * (1 + eps), turns, rf, integ, **kw)
-    amp = np.maximum(err(zb, db, za, da), err(zc, dc, za, da)) / eps
-    return 8 * 2.0 ** -53 * turns * np.maximum(amp, 1.0), amp
+    return check_particles(
+        e, np.zeros(e.size, dtype=bool), turns,
+        lambda m: amplification(oracle.track_rf2, z0[m], dp0[m], turns, rf, integ, err=err, **kw),
+        label=label)
 
 
 def run(ltrk, z0, dp0, turns, rf, integ):
@@ -68,13 +67,7 @@ def test_extended_map_against_oracle(ltrk, integ, rf):
     z, dp, mom = run(ltrk, z0, dp0, 1000, rf, integ)
     zr, dr, mr = oracle.track_rf2(z0, dp0, 1000, rf, integ)
     e = err(z, dp, zr, dr)
-    tol, amp = tolerance(z0, dp0, 1000, rf, integ)
-    assert amp.max() < 1e3  # no chaotic particle in this bunch
-    assert np.all(np.isfinite(e))
-    worst = np.argmax(e / tol)
-    assert np.all(e <= tol), (e[worst], tol[worst], amp[worst])
-    print("%s: e p50 %.2e max %.2e, max e/tol %.2f" % (integ, np.median(e), e.max(),
-                                                       (e / tol).max()))
+    check(e, z0, dp0, 1000, rf, integ, "rf2 %s" % integ)
     assert moment_error(mom, mr).max() <= 1e-10
 
 
@@ -90,14 +83,18 @@ def test_reduces_to_single_harmonic_kernel(ltrk):
     # The two kernels reduce the RF phase differently (the single-harmonic one
     # from the unrounded product s z, the extended one from u = fl(s z)), so
     # they agree to rounding: 1e-13, or the rounding bound of a particle's
-    # own orbit where that is larger.
+    # own orbit where that is larger, never above the cap of the oracle bounds.
     e = err(z, dp, zs.cpu().numpy(), ds.cpu().numpy())
     tol = np.full_like(e, 1e-13)
     over = e > tol
     if np.any(over):
         amp = amplification(oracle.track, z0[over], dp0[over], 500, SPS_RING, "leapfrog")
-        tol[over] = np.maximum(tol[over], rounding_tolerance(amp, 500))
+        tol[over] = np.minimum(np.maximum(tol[over], rounding_tolerance(amp, 500)),
+                               amplified_cap(500))
+    print("rf2 vs single-harmonic kernel: e max %.2e, %d of %d over 1e-13"
+          % (e.max(), over.sum(), e.size))
     assert np.all(e <= tol), (e.max(), over.sum())
+    assert over.sum() <= 0.005 * e.size
     assert moment_error(mom, ms.cpu().numpy()).max() <= 1e-13
 
 
@@ -110,8 +107,5 @@ def test_extended_paper_scale_sampled(ltrk):
     zr, dr, _ = oracle.track_rf2(z0[idx], dp0[idx], T, BLM, "leapfrog", with_moments=False,
                                  threads=1)
     e = err(z[idx], dp[idx], zr, dr)
-    tol, amp = tolerance(z0[idx], dp0[idx], T, BLM, "leapfrog")
-    assert np.all(e <= tol), (e / tol).max()
-    print("paper scale: e p50 %.2e max %.2e, max e/tol %.2f, amp max %.1f"
-          % (np.median(e), e.max(), (e / tol).max(), amp.max()))
+    check(e, z0[idx], dp0[idx], T, BLM, "leapfrog", "rf2 1e6 x 1e4 sample")
     assert moment_error(mom[-1:], oracle.moments(z, dp)[None, :]).max() <= 1e-12

@@ -205,6 +205,35 @@ def test_calls_captured_by_the_caller_replay_exactly(ltrk):
         ltrk.ltrk_set_plan()
 
 
+def test_capture_refusals_enqueue_nothing(ltrk):
+    """Under a caller's stream capture, a batched call (it uploads tables) and
+    a call that would have to grow its stream's moment scratch return
+    EUNSUPPORTED before enqueueing anything: the captured graph is empty and
+    the arrays are untouched."""
+    z0, dp0 = gaussian_bunch(4096, 0.2, 1e-3, 22)
+    s = torch.cuda.Stream()  # a new stream: no scratch yet
+    z, dp = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+    mom = torch.empty((10, 5), dtype=torch.float64, device="cuda")
+    bunches = [dict(z=z, dp=dp, ring=SPS_RING, moments=mom)]
+    torch.cuda.synchronize()
+    codes = []
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        for call in (lambda: ltrk.ltrk_track_batched(bunches, 10, "leapfrog", "f64", stream=s),
+                     lambda: ltrk.ltrk_track_f64(z, dp, 10, SPS_RING, "leapfrog", mom,
+                                                 stream=s)):
+            try:
+                call()
+                codes.append(0)
+            except ltrk.LtrkError as err:
+                codes.append(err.code)
+    torch.cuda.synchronize()
+    assert codes == [ltrk.LTRK_EUNSUPPORTED, ltrk.LTRK_EUNSUPPORTED]
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(z.cpu().numpy(), z0) and np.array_equal(dp.cpu().numpy(), dp0)
+
+
 def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
     n = 200_000
     best = ltrk.ltrk_autotune("leapfrog", "f64", n)
@@ -227,3 +256,5 @@ def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
     e = bucket_error(z.cpu().numpy()[idx], dp.cpu().numpy()[idx], zr, dr, SPS_RING)
     near = near_separatrix(z0[idx], dp0[idx], SPS_RING)
     assert e[~near].max() <= 1e-12
+    if near.any():
+        assert e[near].max() <= 1e-10
