@@ -138,6 +138,25 @@ int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out);
 int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_ring* ring,
                    int integrator, ltrk_moments* moments, void* stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ltrk_track_f64 with the same
+ * arguments, plan and results (bit for bit), whose moment partials live in a
+ * fixed array of LTRK_NOALLOC_SCRATCH_BYTES on each device, held from the
+ * first such call on that device (which looks up the array's address) until
+ * the process ends. It allocates no device or host memory, builds no graph and
+ * is not timed by ltrk_timing_enable; its launches go directly onto `stream`
+ * in chunks of turns whose partials fit the array. EINVAL, before anything is
+ * enqueued, for arguments ltrk_track_f64 rejects and when moments are
+ * requested for a bunch whose partials of one turn exceed the array (beyond
+ * about 8.5e8 particles at 8 per lane). All calls on one device share its array: calls that
+ * overlap on that device (other streams or threads) race and give wrong
+ * moments; the array's contents between calls are unspecified (every row a
+ * call reads is written by that call first). */
+#define LTRK_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ltrk_track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
+                           const ltrk_ring* ring, int integrator, ltrk_moments* moments,
+                           void* stream);
+
 /* Same with the FP32 + Kahan-compensation state (LTRK_F32C). The four arrays
  * of n floats are all state: z = z_hi - z_comp, dp = dp_hi - dp_comp. Start
  * from comp = fl32(hi - value) (or zero); keep them between calls. */

@@ -196,6 +196,8 @@ _SIGS = {
     "ltrk_abi_version": ([], ctypes.c_int),
     "ltrk_derive": ([P(Ring), P(Derived)], ctypes.c_int),
     "ltrk_track_f64": ([c_vp, c_vp, c_i64, c_i64, P(Ring), ctypes.c_int, c_vp, c_vp], ctypes.c_int),
+    "ltrk_track_f64_noalloc": ([c_vp, c_vp, c_i64, c_i64, P(Ring), ctypes.c_int, c_vp, c_vp],
+                               ctypes.c_int),
     "ltrk_track_f32c": ([c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, P(Ring), ctypes.c_int, c_vp, c_vp],
                         ctypes.c_int),
     "ltrk_track_rf2_f64": ([c_vp, c_vp, c_i64, c_i64, P(Rf2), ctypes.c_int, c_vp, c_vp],
@@ -312,6 +314,18 @@ def ltrk_track_f64(z, dp, turns: int, ring, integrator="leapfrog", moments=None,
                                _dev_ptr(dp, torch.float64, n, "dp"), n, int(turns),
                                ctypes.byref(Ring.of(ring)), _integ(integrator),
                                _mom_ptr(moments, int(turns)), _stream(stream)))
+
+
+def ltrk_track_f64_noalloc(z, dp, turns: int, ring, integrator="leapfrog", moments=None,
+                           stream=None):
+    """ltrk_track_f64 without any allocation (moment partials in the library's
+    fixed per-device array); same arguments and results."""
+    import torch
+    n = z.numel()
+    _check(_lib.ltrk_track_f64_noalloc(_dev_ptr(z, torch.float64, None, "z"),
+                                       _dev_ptr(dp, torch.float64, n, "dp"), n, int(turns),
+                                       ctypes.byref(Ring.of(ring)), _integ(integrator),
+                                       _mom_ptr(moments, int(turns)), _stream(stream)))
 
 
 def ltrk_track_f32c(z, dp, z_comp, dp_comp, turns: int, ring, integrator="leapfrog",

@@ -904,13 +904,18 @@ void key_add(std::string& k, const T& v) {
 
 // Rows (turns) of partial sums per finalize chunk for `waves_total` waves,
 // a multiple of K unless the whole run is shorter.
-int64_t chunk_rows(int64_t turns, int64_t K, int64_t cols_total, bool two_stage) {
+int64_t chunk_rows(int64_t turns, int64_t K, int64_t cols_total, bool two_stage,
+                   size_t cap_bytes) {
   const int64_t per_row = cols_total * 5 * static_cast<int64_t>(sizeof(double));
-  int64_t cap = static_cast<int64_t>(scratch_cap_bytes()) / std::max<int64_t>(per_row, 1);
+  int64_t cap = static_cast<int64_t>(cap_bytes) / std::max<int64_t>(per_row, 1);
   if (two_stage && cap > 65535) cap = 65535;  // grid rows of the group-sum stage
   if (cap >= turns) return turns;
   if (cap >= K) return (cap / K) * K;
   return cap;  // may be < K (the caller then shortens launches)
+}
+
+int64_t chunk_rows(int64_t turns, int64_t K, int64_t cols_total, bool two_stage) {
+  return chunk_rows(turns, K, cols_total, two_stage, scratch_cap_bytes());
 }
 
 }  // namespace
@@ -1057,6 +1062,134 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
     }
   }
   return finish(c, key, seq, s, plan.use_graph != 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tracking without allocation (ltrk_track_f64_noalloc)
+
+namespace noalloc {
+
+// The moment-partial scratch of the allocation-free entry point: one array on
+// every device the library runs on, for the life of the process. In host code
+// the name `scratch` stands for a host-side stand-in, not device memory: host
+// code uses only the device address that hipGetSymbolAddress returned for
+// the device (device_scratch), for kernel arguments as for anything else.
+constexpr size_t kBytes = LTRK_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+
+namespace {
+std::mutex g_mu;
+void* g_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Set-up, once per device (dev is current): the device address of `scratch`,
+// and the plan lookup's first use on the device (it caches the device's
+// architecture name), so that later calls allocate nothing on the host either.
+static int device_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LTRK_EINVAL, "device %d: the allocation-free path serves devices 0 to %d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> g(g_mu);
+  if (!g_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "hipGetSymbolAddress of the allocation-free scratch");
+    }
+    (void)choose_plan(LTRK_LEAPFROG, LTRK_F64, 1, false);
+    g_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_ptr[dev]);
+  return LTRK_OK;
+}
+
+}  // namespace noalloc
+
+// ltrk_track_f64 with the moment partials in noalloc::scratch: the same plan
+// (hence the same results, bit for bit), launched directly on the stream in
+// chunks of turns whose partials fit the array; no graph (instantiating one
+// allocates), no launch timing, no hipMalloc or hipFree, no host containers.
+static int track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
+                             const ltrk_ring* ring, int integrator, ltrk_moments* mom,
+                             hipStream_t s) {
+  int rc = validate_ring(ring);
+  if (rc) return rc;
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (n < 0) return fail(LTRK_EINVAL, "n must be >= 0");
+  if (turns < 0) return fail(LTRK_EINVAL, "turns must be >= 0");
+  if (turns > INT32_MAX) return fail(LTRK_EINVAL, "turns must be < 2^31");
+  if (turns == 0) return LTRK_OK;
+  if (mom && (rc = check_device_range(mom, static_cast<size_t>(turns) * sizeof(ltrk_moments),
+                                      "moments")))
+    return rc;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  double* base = nullptr;
+  if ((rc = noalloc::device_scratch(dev, &base))) return rc;
+  if (n == 0) {
+    if (!mom) return LTRK_OK;
+    hipError_t e = launch_fill_nan(mom, turns, s);
+    return e == hipSuccess ? LTRK_OK : fail_hip(e, "fill moments");
+  }
+  const size_t bytes = static_cast<size_t>(n) * sizeof(double);
+  if ((rc = check_device_range(z, bytes, "z"))) return rc;
+  if ((rc = check_device_range(dp, bytes, "dp"))) return rc;
+  bool default_plan = false;
+  const ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false, &default_plan);
+  BunchDev b;
+  std::memset(&b, 0, sizeof(b));
+  b.z = z;
+  b.dp = dp;
+  b.n = n;
+  b.waves = waves_for(n, plan.ppl);
+  b.integrator = integrator;
+  b.dtype = LTRK_F64;
+  b.active = 1;
+  make_coeffs(*ring, integrator, &b.c);
+  int64_t K = plan.turns_per_launch;
+  if (mom && default_plan)
+    K = default_turns_for_partials(K, 5 * b.waves * static_cast<int64_t>(sizeof(double)));
+  int64_t rows = turns;
+  const int64_t groups = finalize_groups(b.waves);
+  if (mom) {
+    const int64_t row_bytes = 5 * scratch_cols(b.waves) * static_cast<int64_t>(sizeof(double));
+    rows = chunk_rows(turns, K, scratch_cols(b.waves), groups > 1, noalloc::kBytes);
+    if (rows < 1)
+      return fail(LTRK_EINVAL,
+                  "%lld particles need %lld bytes of moment partials per turn; the "
+                  "allocation-free scratch holds %zu (pass moments = NULL, or use "
+                  "ltrk_track_f64)",
+                  static_cast<long long>(n), static_cast<long long>(row_bytes), noalloc::kBytes);
+    K = std::min<int64_t>(K, rows);
+  }
+  for (int64_t c0 = 0; c0 < turns; c0 += rows) {
+    const int64_t len = std::min(rows, turns - c0);
+    for (int64_t j = 0; j < len; j += K) {
+      BunchDev bl = b;
+      bl.turns = static_cast<int32_t>(std::min(K, len - j));
+      bl.partials = mom ? base : nullptr;
+      hipError_t e = launch_track_single(bl, static_cast<int32_t>(j), plan.ppl, plan.block, s);
+      if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    }
+    if (mom) {
+      FinalizeDev f;
+      std::memset(&f, 0, sizeof(f));
+      f.partials = base;
+      f.stage = base + rows * 5 * b.waves;
+      f.waves = b.waves;
+      f.groups = groups;
+      f.n = n;
+      f.out = mom + c0;
+      f.rows = static_cast<int32_t>(len);
+      hipError_t e = launch_finalize_single(f, s);
+      if (e != hipSuccess) return fail_hip(e, "finalize launch");
+    }
+  }
+  return LTRK_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1660,6 +1793,15 @@ int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_r
   LTRK_GUARD({
     return track_single(z, dp, nullptr, nullptr, n, turns, ring, integrator, LTRK_F64, moments,
                         static_cast<hipStream_t>(stream));
+  })
+}
+
+int ltrk_track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
+                           const ltrk_ring* ring, int integrator, ltrk_moments* moments,
+                           void* stream) {
+  LTRK_GUARD({
+    return track_f64_noalloc(z, dp, n, turns, ring, integrator, moments,
+                             static_cast<hipStream_t>(stream));
   })
 }
 

@@ -1,0 +1,74 @@
+"""The allocation-free entry point (ltrk_track_f64_noalloc) against
+ltrk_track_f64 through the C ABI: same plan, so the same particles and moment
+rows bit for bit. Two calls in a row, the second on a smaller bunch (the
+fixed per-device array keeps the first call's contents); a call long enough
+to be finalized in several chunks of the array; an empty bunch; and the
+refusal of a bunch whose partials of one turn exceed the array."""
+import numpy as np
+import pytest
+
+from synth import SPS_RING, SIGMA_DP, SIGMA_Z, gaussian_bunch
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ltrk():
+    import paper_1610_05801_amd as m
+    m.ltrk_set_plan()
+    yield m
+    m.ltrk_set_plan()
+
+
+def run(fn, z0, dp0, turns, integ, stream):
+    z = torch.as_tensor(z0).cuda()
+    dp = torch.as_tensor(dp0).cuda()
+    mom = torch.empty((turns, 5), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        fn(z, dp, turns, SPS_RING, integ, mom, stream=stream)
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy()
+
+
+def same(a, b, label):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y), label
+
+
+def test_two_calls_second_smaller(ltrk):
+    s = torch.cuda.Stream()
+    for n, turns, integ in ((300_001, 700, "leapfrog"), (4_097, 333, "ruth4")):
+        z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, 60_000 + n)
+        got = run(ltrk.ltrk_track_f64_noalloc, z0, dp0, turns, integ, s)
+        ref = run(ltrk.ltrk_track_f64, z0, dp0, turns, integ, s)
+        assert np.isfinite(got[2]).all()
+        same(got, ref, (n, turns, integ))
+
+
+def test_chunked_by_the_fixed_array(ltrk):
+    """1e6 particles at 8 per lane: 78 KB of partials per turn, so the 64 MiB
+    array holds 858 turns and 2000 turns run in three chunks."""
+    s = torch.cuda.Stream()
+    z0, dp0 = gaussian_bunch(1_000_000, SIGMA_Z, SIGMA_DP, 61_000)
+    got = run(ltrk.ltrk_track_f64_noalloc, z0, dp0, 2000, "euler_cromer", s)
+    ref = run(ltrk.ltrk_track_f64, z0, dp0, 2000, "euler_cromer", s)
+    same(got, ref, "chunked")
+
+
+def test_empty_bunch_and_refusal(ltrk):
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    mom = torch.zeros((4, 5), dtype=torch.float64, device="cuda")
+    ltrk.ltrk_track_f64_noalloc(z, z, 4, SPS_RING, "leapfrog", mom)
+    torch.cuda.synchronize()
+    assert torch.isnan(mom).all()
+    # one turn of partials for 9e8 particles (8 per lane) exceeds the array
+    n = 900_000_000
+    big_z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    big_d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    mom1 = torch.empty((1, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(ltrk.LtrkError) as err:
+        ltrk.ltrk_track_f64_noalloc(big_z, big_d, 1, SPS_RING, "leapfrog", mom1)
+    assert err.value.code == ltrk.LTRK_EINVAL
+    del big_z, big_d
+    torch.cuda.empty_cache()
