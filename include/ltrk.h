@@ -129,7 +129,12 @@ int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out);
 /* Track n particles for `turns` turns in place (FP64 state).
  * z, dp: device arrays of n doubles, updated in place.
  * moments: device array of `turns` rows or NULL; row t receives the moments
- *   after turn t+1 (turn-0 moments: ltrk_moments_f64).
+ *   after turn t+1 (turn-0 moments: ltrk_moments_f64). The sums behind them
+ *   are taken about a centre fixed for the call (the mean of an evenly
+ *   strided sample of up to 4096 particles of the initial state where it
+ *   lies more than 4 sample rms from zero, else zero), so a bunch far from
+ *   the origin keeps its accuracy; a centroid that moves by A rms away from
+ *   that centre during the call loses about (A^2) ulp of the variance.
  * integrator: LTRK_EULER_CROMER .. LTRK_RK4.
  * Any finite z is valid (no aperture, no wrapping): the RF phase 2hz/C is
  * reduced to [-1/2, 1/2] exactly, from the unrounded product while every
@@ -363,8 +368,11 @@ int ltrk_tune_cache_load(const char* path);
  * (cached apart from the untimed one) with event-record nodes between its
  * segments of consecutive tracking or finalize launches, fresh events at
  * every replay: a segment's time covers its launches and the short gaps
- * between them, and the graph keeps its own launch cadence. ltrk_timing_take
- * synchronises the recorded events, returns the totals and clears them. */
+ * between them, and the graph keeps its own launch cadence. A call with
+ * moments counts two kinds of moment launches as finalize launches: the one
+ * that fixes the centre of its moment sums before its first turn, and the
+ * finalize after every chunk of turns. ltrk_timing_take synchronises the
+ * recorded events, returns the totals and clears them. */
 typedef struct ltrk_timing {
     int64_t track_launches;
     double track_ms;
@@ -417,7 +425,8 @@ typedef struct ltrk_engine_stats {
 
 int ltrk_engine_create(int device, int64_t hbm_budget_bytes, int max_slots, ltrk_engine** out);
 /* Bytes of arena a job needs: state (16 B per particle) + moment rows (40 B
- * per turn), each rounded up to 256 B. */
+ * per turn), each rounded up to 256 B, + 256 B for the centre of its moment
+ * sums. */
 int ltrk_engine_footprint(const ltrk_job* job, int64_t* bytes);
 /* Admit a job: LTRK_EAGAIN if no slot is free, the arena has no block large
  * enough now, or the running jobs and this one would need more moment-partial

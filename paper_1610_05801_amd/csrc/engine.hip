@@ -94,14 +94,17 @@ struct Slot {
   void* zc = nullptr;
   void* dc = nullptr;
   ltrk_moments* mom = nullptr;
+  double* centre = nullptr;  // centre of the job's moment sums (k_centre at admission)
   Coeffs c;
   int64_t waves = 0;
   hipEvent_t last = nullptr;  // recorded after the slot's latest enqueued work
 };
 
+// State, moment rows and the centre of the moment sums, each 256-B aligned.
 int64_t footprint(int64_t n, int64_t turns) {
   return static_cast<int64_t>(round_up(static_cast<size_t>(n) * 16, 256) +
-                              round_up(static_cast<size_t>(turns) * sizeof(ltrk_moments), 256));
+                              round_up(static_cast<size_t>(turns) * sizeof(ltrk_moments), 256) +
+                              kCentreDoubles * sizeof(double));
 }
 
 int validate_job(const ltrk_job* j) {
@@ -277,6 +280,7 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
     d.n = s.n;
     d.waves = s.waves;
     d.partials = e->partials + off;
+    d.centre = s.centre;
     d.c = s.c;
     d.integrator = s.integrator;
     d.dtype = s.dtype;
@@ -290,6 +294,7 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
     f.groups = finalize_groups(s.waves);
     f.n = s.n;
     f.out = s.mom + s.done_turns;
+    f.centre = s.centre;
     f.rows = static_cast<int32_t>(rows);
     off += static_cast<size_t>(rows) * 5 * scratch_cols(s.waves);
     max_rows = std::max<int32_t>(max_rows, static_cast<int32_t>(rows));
@@ -488,6 +493,9 @@ int ltrk_engine_admit(ltrk_engine* e, const ltrk_job* job, int* slot) {
     s.zc = job->dtype == LTRK_F32C ? base + 2 * n * elem : nullptr;
     s.dc = job->dtype == LTRK_F32C ? base + 3 * n * elem : nullptr;
     s.mom = reinterpret_cast<ltrk_moments*>(base + round_up(n * 16, 256));
+    s.centre = reinterpret_cast<double*>(
+        base + round_up(n * 16, 256) +
+        round_up(static_cast<size_t>(job->turns) * sizeof(ltrk_moments), 256));
     // Synchronous copies: the caller's host arrays are free to go once admit
     // returns. The arena block is idle (its previous job was retired after
     // its last step completed), so no ordering with the engine stream is needed.
@@ -500,6 +508,14 @@ int ltrk_engine_admit(ltrk_engine* e, const ltrk_job* job, int* slot) {
       s.used = false;
       e->arena.release(off, need);
       return fail_hip(er, "job upload");
+    }
+    // the centre of the job's moment sums, from its initial state, as a
+    // standalone call computes it (the same kernel and sample)
+    if ((er = launch_centre(CentreDev{s.z, s.dp, s.zc, s.dc, s.n, s.dtype, s.centre},
+                            e->stream)) != hipSuccess) {
+      s.used = false;
+      e->arena.release(off, need);
+      return fail_hip(er, "job centre");
     }
     hipEventRecord(s.last, e->stream);
     *slot = free_slot;

@@ -49,6 +49,11 @@ hipError_t launch_finalize_single(const FinalizeDev& f, hipStream_t s);
 // max_groups is the largest f.groups in the table (two-stage reduction when > 1).
 hipError_t launch_finalize_multi(const FinalizeDev* fs, int nf, int rows, int64_t out_row0,
                                  int64_t max_groups, hipStream_t s);
+// The centre of a bunch's moment sums (kCentreSample) into c.out[0..1].
+hipError_t launch_centre(const CentreDev& c, hipStream_t s);
+// The same for every bunch of a device table that computes moments (into
+// its b.centre).
+hipError_t launch_centre_bunches(const BunchDev* bunches, int nb, hipStream_t s);
 hipError_t launch_fill_nan(ltrk_moments* out, int64_t rows, hipStream_t s);
 hipError_t launch_fill_probe(double* z, double* dp, int64_t n, hipStream_t s);
 

@@ -180,8 +180,15 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  auto loop = [&](auto exact) {
+  const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
+  bool live[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) live[p] = first + static_cast<int64_t>(p) * kWave < b.n;
+  const bool tail = (w + 1) * static_cast<int64_t>(kWave * P) > b.n;
+  auto loop = [&](auto exact, auto shift, auto tail_tile) {
     constexpr bool EXACT = decltype(exact)::value;
+    constexpr bool SHIFT = decltype(shift)::value;
+    constexpr bool TAIL = decltype(tail_tile)::value;
     for (int t = 0; t < turns; t += kFlushTurns) {
       const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
       for (int j = 0; j < nb; ++j) {
@@ -192,10 +199,7 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
           if constexpr (MOM) {
             const double zv = static_cast<double>(zh[p]) - static_cast<double>(zc[p]);
             const double dv = static_cast<double>(dh[p]) - static_cast<double>(dc[p]);
-            if (p == 0)
-              s = first_sums(zv, dv);
-            else
-              accumulate(s, zv, dv);
+            add_particle<SHIFT, TAIL>(s, p, zv, dv, cen, live[p]);
           }
         }
         if constexpr (MOM) stage_sums(buf, j, s, lane);
@@ -214,10 +218,20 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
     za[p] = __builtin_fabs(static_cast<double>(zh[p])) + __builtin_fabs(static_cast<double>(zc[p]));
     da[p] = __builtin_fabs(static_cast<double>(dh[p])) + __builtin_fabs(static_cast<double>(dc[p]));
   }
-  if (in_exact_range<P>(b.c, za, da, turns))
-    loop(std::true_type{});
-  else
-    loop(std::false_type{});
+  auto shifted = [&](auto exact) {
+    if (tail)
+      loop(exact, std::true_type{}, std::true_type{});
+    else
+      loop(exact, std::true_type{}, std::false_type{});
+  };
+  if (in_exact_range<P>(b.c, za, da, turns)) {
+    if (is_zero(cen))
+      loop(std::true_type{}, std::false_type{}, std::false_type{});
+    else
+      shifted(std::true_type{});
+  } else {
+    shifted(std::false_type{});
+  }
   if constexpr (INTEG != kMeasureOnly) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -309,7 +323,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_track_mixed(const BunchDev* __res
 // or group sums (second stage).
 // `p` points at one row's 5 x cols sums, the result goes to *out.
 __device__ __forceinline__ void finalize_row(const double* __restrict__ p, int64_t cols,
-                                             int64_t n, ltrk_moments* out) {
+                                             int64_t n, const double* centre,
+                                             ltrk_moments* out) {
   const int lane = threadIdx.x & (kWave - 1);
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t w = lane; w < cols; w += kWave) {
@@ -322,7 +337,10 @@ __device__ __forceinline__ void finalize_row(const double* __restrict__ p, int64
     for (int m = 0; m < 5; ++m) s[m] += __shfl_xor(s[m], off);
   }
   if (lane == 0) {
+    // sums of z - c_z and dp - c_dp: the means relative to the centre, then
+    // the centre added back
     const double nd = static_cast<double>(n);
+    const Centre c = centre_of(centre);
     const double mz = s[0] / nd;
     const double md = s[2] / nd;
     double vz = s[1] / nd - mz * mz;
@@ -332,9 +350,9 @@ __device__ __forceinline__ void finalize_row(const double* __restrict__ p, int64
     vd = vd > 0.0 ? vd : 0.0;
     const double e2 = vz * vd - cov * cov;
     ltrk_moments o;
-    o.mean_z = mz;
+    o.mean_z = c.z == 0.0 ? mz : c.z + mz;
     o.rms_z = __builtin_sqrt(vz);
-    o.mean_dp = md;
+    o.mean_dp = c.d == 0.0 ? md : c.d + md;
     o.rms_dp = __builtin_sqrt(vd);
     o.emit_rms = __builtin_sqrt(e2 > 0.0 ? e2 : 0.0);
     *out = o;
@@ -393,11 +411,11 @@ __device__ __forceinline__ void finalize_bunch_row(const FinalizeDev& f, ltrk_mo
                                                    int row) {
   const int planes = planes_of(f);
   if (f.groups > 1)
-    finalize_row(f.stage + static_cast<int64_t>(row) * 5 * f.groups, f.groups, f.n,
+    finalize_row(f.stage + static_cast<int64_t>(row) * 5 * f.groups, f.groups, f.n, f.centre,
                  out + static_cast<int64_t>(row) * planes);
   else
     finalize_row(f.partials + static_cast<int64_t>(row) * 5 * planes * f.waves, f.waves, f.n,
-                 out + static_cast<int64_t>(row) * planes);
+                 f.centre, out + static_cast<int64_t>(row) * planes);
 }
 
 __global__ __launch_bounds__(256) void k_finalize_single(FinalizeDev f) {
@@ -413,6 +431,82 @@ __global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeDev* __res
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (f.out == nullptr || row >= rows || row >= f.rows) return;
   finalize_bunch_row(f, f.out + out_row0 * planes_of(f), row);
+}
+
+// ---------------------------------------------------------------------------
+// Centre of the moment sums (one block of 256 threads per bunch)
+
+// Block-wide sum of one value per thread in a fixed order: xor butterfly in
+// each wave, then the four wave totals pairwise. Every thread gets the total.
+__device__ __forceinline__ double block_sum4(double x, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = x + __shfl_xor(x, off);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();  // red may still be read from a previous call
+  if ((threadIdx.x & (kWave - 1)) == 0) red[wave] = x;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Mean and variance of an evenly strided sample of S = min(n, kCentreSample)
+// particles (sample k is particle floor(k n / S)), two-pass; the centre is the
+// sample mean where it lies more than kCentreRatio sample rms from zero, else
+// 0 (also for a sample without spread, or a non-finite one).
+__device__ void centre_block(const CentreDev& c) {
+  __shared__ double red[4];
+  constexpr int kPer = kCentreSample / 256;
+  const int64_t S = c.n < kCentreSample ? c.n : kCentreSample;
+  double zv[kPer], dv[kPer];
+  double sz = 0.0, sd = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int64_t k = threadIdx.x + 256 * j;
+    zv[j] = 0.0;
+    dv[j] = 0.0;
+    if (k < S) {
+      // floor(k n / S) without overflow: n = q S + r, k r < S^2
+      const int64_t i = k * (c.n / S) + (k * (c.n % S)) / S;
+      if (c.dtype == kF64) {
+        zv[j] = static_cast<const double*>(c.z)[i];
+        dv[j] = static_cast<const double*>(c.dp)[i];
+      } else {
+        zv[j] = static_cast<double>(static_cast<const float*>(c.z)[i]) -
+                static_cast<double>(static_cast<const float*>(c.z_comp)[i]);
+        dv[j] = static_cast<double>(static_cast<const float*>(c.dp)[i]) -
+                static_cast<double>(static_cast<const float*>(c.dp_comp)[i]);
+      }
+      sz += zv[j];
+      sd += dv[j];
+    }
+  }
+  const double Sd = static_cast<double>(S);
+  const double mz = block_sum4(sz, red) / Sd;
+  const double md = block_sum4(sd, red) / Sd;
+  double qz = 0.0, qd = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (threadIdx.x + 256 * j < S) {
+      qz = __builtin_fma(zv[j] - mz, zv[j] - mz, qz);
+      qd = __builtin_fma(dv[j] - md, dv[j] - md, qd);
+    }
+  }
+  const double vz = block_sum4(qz, red) / Sd;
+  const double vd = block_sum4(qd, red) / Sd;
+  constexpr double r2 = kCentreRatio * kCentreRatio;
+  if (threadIdx.x == 0) {
+    c.out[0] = (vz > 0.0 && mz * mz > r2 * vz && __builtin_isfinite(mz * mz)) ? mz : 0.0;
+    c.out[1] = (vd > 0.0 && md * md > r2 * vd && __builtin_isfinite(md * md)) ? md : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_centre(CentreDev c) { centre_block(c); }
+
+// Block b: the centre of bunches[b] when it computes moments.
+__global__ __launch_bounds__(256) void k_centre_bunches(const BunchDev* __restrict__ bunches) {
+  const BunchDev b = bunches[blockIdx.x];
+  if (!b.partials || !b.centre || b.n <= 0) return;
+  centre_block(CentreDev{b.z, b.dp, b.z_comp, b.dp_comp, b.n, b.dtype,
+                         const_cast<double*>(b.centre)});
 }
 
 __global__ void k_fill_nan(ltrk_moments* out, int64_t rows) {
@@ -558,6 +652,18 @@ hipError_t launch_finalize_multi(const FinalizeDev* fs, int nf, int rows, int64_
   }
   const int blocks = (rows + 3) / 4;
   hipLaunchKernelGGL(k_finalize_multi, dim3(blocks, nf), dim3(256), 0, s, fs, rows, out_row0);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre(const CentreDev& c, hipStream_t s) {
+  if (c.n <= 0 || !c.out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_centre, dim3(1), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre_bunches(const BunchDev* bunches, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_centre_bunches, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, bunches);
   return hipGetLastError();
 }
 

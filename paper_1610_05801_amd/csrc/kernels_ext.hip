@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "ltrk_device.h"
 #include "ltrk_device_ext.h"
@@ -83,23 +85,31 @@ __device__ __forceinline__ void wave_ext(const BunchDev& b, const Turn& turn, in
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  for (int t = 0; t < turns; t += kFlushTurns) {
-    const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
-    for (int j = 0; j < nb; ++j) {
-      turn.template all<P, TAIL>(turn.at(t + j), z, d, live);
-      if constexpr (MOM) {
-        Sums s = first_sums(z[0], d[0]);
+  const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
+  auto loop = [&](auto shift) {
+    constexpr bool SHIFT = decltype(shift)::value;
+    for (int t = 0; t < turns; t += kFlushTurns) {
+      const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
+      for (int j = 0; j < nb; ++j) {
+        turn.template all<P, TAIL>(turn.at(t + j), z, d, live);
+        if constexpr (MOM) {
+          Sums s;
 #pragma unroll
-        for (int p = 1; p < P; ++p) accumulate(s, z[p], d[p]);
-        stage_sums(buf, j, s, lane);
+          for (int p = 0; p < P; ++p) add_particle<SHIFT, TAIL>(s, p, z[p], d[p], cen, live[p]);
+          stage_sums(buf, j, s, lane);
+        }
+      }
+      if constexpr (MOM) {
+        wave_sync();
+        flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
+        wave_sync();
       }
     }
-    if constexpr (MOM) {
-      wave_sync();
-      flush_rows(buf, nb * 5, out + static_cast<int64_t>(t) * 5 * b.waves, b.waves, lane);
-      wave_sync();
-    }
-  }
+  };
+  if (is_zero(cen))
+    loop(std::false_type{});
+  else
+    loop(std::true_type{});
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int64_t i = first + static_cast<int64_t>(p) * kWave;
@@ -184,6 +194,9 @@ __device__ __forceinline__ void wave_6d(const Bunch6Dev& b, const Coeffs6d& c, i
   }
   const Rf2Src src{c.rf};
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 15 * b.waves + w : nullptr;
+  // the (z, dp) sums about the call's centre (the transverse centroids turn
+  // with the betatron phase, so no fixed centre follows them: theirs is 0)
+  const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
   for (int t = 0; t < turns; t += kFlushTurns6d) {
     const int nb = turns - t < kFlushTurns6d ? turns - t : kFlushTurns6d;
     for (int j = 0; j < nb; ++j) {
@@ -196,13 +209,12 @@ __device__ __forceinline__ void wave_6d(const Bunch6Dev& b, const Coeffs6d& c, i
       }
       turn_ext<INTEG, false, H, P, TAIL>(s6[0], s6[1], live, c.rf, src);
       if constexpr (MOM) {
-        Sums sl = first_sums(s6[0][0], s6[1][0]), sx = first_sums(s6[2][0], s6[3][0]),
-             sy = first_sums(s6[4][0], s6[5][0]);
+        Sums sl, sx, sy;
 #pragma unroll
-        for (int p = 1; p < P; ++p) {
-          accumulate(sl, s6[0][p], s6[1][p]);
-          accumulate(sx, s6[2][p], s6[3][p]);
-          accumulate(sy, s6[4][p], s6[5][p]);
+        for (int p = 0; p < P; ++p) {
+          add_particle<true, TAIL>(sl, p, s6[0][p], s6[1][p], cen, live[p]);
+          add_particle<false, TAIL>(sx, p, s6[2][p], s6[3][p], cen, live[p]);
+          add_particle<false, TAIL>(sy, p, s6[4][p], s6[5][p], cen, live[p]);
         }
         stage_sums(buf, 3 * j + 0, sl, lane);
         stage_sums(buf, 3 * j + 1, sx, lane);

@@ -100,8 +100,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c
         if (live[p] && slice_of(w, z[p]) >= 0) d[p] = d[p] - w.kappa * potential_at(w, pot, z[p]);
     }
     if constexpr (MOM) {
+      // about the call's centre (HBM-bound kernel: the subtractions cost no time)
+      const Centre cen = centre_of(b.centre);
 #pragma unroll
-      for (int p = 0; p < P; ++p) accumulate(s, z[p], d[p]);
+      for (int p = 0; p < P; ++p)
+        accumulate(s, live[p] ? z[p] - cen.z : 0.0, live[p] ? d[p] - cen.d : 0.0);
     }
     if constexpr (STEP) {
       turn_ext<INTEG, false, H, P, true>(z, d, live, c, src);

@@ -60,6 +60,8 @@ struct BunchDev {
   int64_t waves;      // ceil(n / (64 * ppl)) wave tiles
   double* partials;   // [rows][5][waves] per-wave moment sums of this launch's
                       // first turn row; NULL = no moments
+  const double* centre;  // (c_z, c_dp) the moment sums are taken about (see
+                         // k_centre), or NULL for (0, 0)
   Coeffs c;
   int32_t integrator;
   int32_t dtype;
@@ -72,6 +74,28 @@ struct BunchDev {
 struct TileDev {
   int32_t bunch;
   int32_t wave0;
+};
+
+// Moment sums about a centre. One-pass moments from raw sums (sum z, sum z^2,
+// ...) lose (|mean| / rms)^2 ulp of the variance to cancellation, so the
+// sums are taken of z - c_z and dp - c_dp with a centre fixed for a whole
+// call: the mean of an evenly strided sample of up to kCentreSample particles
+// of the call's initial state (k_centre), used where it lies more than
+// kCentreRatio sample rms from zero and (0, 0) elsewhere. A wave whose
+// centre is (0, 0) runs the loop without the two subtractions.
+constexpr int kCentreSample = 4096;
+constexpr double kCentreRatio = 4.0;
+constexpr int kCentreDoubles = 32;  // scratch doubles reserved per centre (256 B)
+
+// Input of k_centre: one bunch's state and where its centre goes.
+struct CentreDev {
+  const void* z;
+  const void* dp;
+  const void* z_comp;  // F32C only
+  const void* dp_comp;
+  int64_t n;
+  int32_t dtype;
+  double* out;  // (c_z, c_dp)
 };
 
 // Per-wave partial sums are added over wave tiles in groups of kGroupWaves;
@@ -91,6 +115,7 @@ struct FinalizeDev {
   int64_t groups;
   int64_t n;
   ltrk_moments* out;
+  const double* centre;  // the sums' centre (c_z, c_dp) of this plane, or NULL
   int32_t rows;
   int32_t planes;  // planes interleaved per row (0 or 1: one; the 6-D map: 3):
                    // partial rows are 5 * planes * waves apart, the plane's

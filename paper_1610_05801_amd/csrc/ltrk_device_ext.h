@@ -60,6 +60,7 @@ struct Bunch6Dev {
   double* y;
   double* yp;
   double* partials;  // [rows][3][5][waves] per-wave sums of the launch's first row, or NULL
+  const double* centre;  // (c_z, c_dp) of the (z, dp) sums, or NULL
   int64_t n;
   int64_t waves;     // ceil(n / (64 * ppl))
   int32_t turns;     // turns of this launch

@@ -990,14 +990,16 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   int64_t rows = turns;
   void* scratch = nullptr;
   const int64_t groups = finalize_groups(b.waves);
+  double* centre = nullptr;
   if (mom) {
     rows = chunk_rows(turns, K, scratch_cols(b.waves), groups > 1);
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)b.waves);
     K = std::min<int64_t>(K, rows);
-    if ((rc = ensure_scratch(c, s,
-                             static_cast<size_t>(rows) * 5 * scratch_cols(b.waves) * sizeof(double),
-                             &scratch)))
+    const size_t part = static_cast<size_t>(rows) * 5 * scratch_cols(b.waves);
+    if ((rc = ensure_scratch(c, s, (part + kCentreDoubles) * sizeof(double), &scratch)))
       return rc;
+    centre = static_cast<double*>(scratch) + part;
+    b.centre = centre;
   }
 
   void* prog_dev = nullptr;
@@ -1023,7 +1025,11 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   key_add(key, mom);
   key_add(key, scratch);
 
-  LaunchSeq seq(count_launches(turns, rows, K, mom ? 1 : 0), s);
+  LaunchSeq seq(count_launches(turns, rows, K, mom ? 1 : 0) + (mom ? 1 : 0), s);
+  if (mom) {
+    const CentreDev cd{z, dp, zc, dc, n, dtype, centre};
+    seq.push({kTimeFinalize, [cd](hipStream_t st) { return launch_centre(cd, st); }});
+  }
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
     for (int64_t j = 0; j < len; j += K) {
@@ -1057,6 +1063,7 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
       f.groups = groups;
       f.n = n;
       f.out = mom + c0;
+      f.centre = centre;
       f.rows = static_cast<int32_t>(len);
       seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
     }
@@ -1155,9 +1162,12 @@ static int track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
     K = default_turns_for_partials(K, 5 * b.waves * static_cast<int64_t>(sizeof(double)));
   int64_t rows = turns;
   const int64_t groups = finalize_groups(b.waves);
+  // the last kCentreDoubles of the array hold the centre of the moment sums
+  double* centre = base + (noalloc::kBytes / sizeof(double) - kCentreDoubles);
   if (mom) {
     const int64_t row_bytes = 5 * scratch_cols(b.waves) * static_cast<int64_t>(sizeof(double));
-    rows = chunk_rows(turns, K, scratch_cols(b.waves), groups > 1, noalloc::kBytes);
+    rows = chunk_rows(turns, K, scratch_cols(b.waves), groups > 1,
+                      noalloc::kBytes - kCentreDoubles * sizeof(double));
     if (rows < 1)
       return fail(LTRK_EINVAL,
                   "%lld particles need %lld bytes of moment partials per turn; the "
@@ -1165,6 +1175,9 @@ static int track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
                   "ltrk_track_f64)",
                   static_cast<long long>(n), static_cast<long long>(row_bytes), noalloc::kBytes);
     K = std::min<int64_t>(K, rows);
+    b.centre = centre;
+    hipError_t e = launch_centre(CentreDev{z, dp, nullptr, nullptr, n, LTRK_F64, centre}, s);
+    if (e != hipSuccess) return fail_hip(e, "centre launch");
   }
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
@@ -1184,6 +1197,7 @@ static int track_f64_noalloc(double* z, double* dp, int64_t n, int64_t turns,
       f.groups = groups;
       f.n = n;
       f.out = mom + c0;
+      f.centre = centre;
       f.rows = static_cast<int32_t>(len);
       hipError_t e = launch_finalize_single(f, s);
       if (e != hipSuccess) return fail_hip(e, "finalize launch");
@@ -1251,13 +1265,16 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   void* scratch = nullptr;
   const int64_t groups = finalize_groups(b.waves);
   const int64_t cols = 3 * scratch_cols(b.waves);  // 3 planes of 5 sums per row
+  double* centre = nullptr;
   if (mom) {
     rows = chunk_rows(turns, K, cols, groups > 1);
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)b.waves);
     K = std::min<int64_t>(K, rows);
-    if ((rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * cols * sizeof(double),
-                             &scratch)))
+    const size_t part = static_cast<size_t>(rows) * 5 * cols;
+    if ((rc = ensure_scratch(c, s, (part + kCentreDoubles) * sizeof(double), &scratch)))
       return rc;
+    centre = static_cast<double*>(scratch) + part;
+    b.centre = centre;
   }
 
   std::string key;
@@ -1270,7 +1287,11 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   key_add(key, mom);
   key_add(key, scratch);
 
-  LaunchSeq seq(count_launches(turns, rows, K, mom ? 3 : 0), s);
+  LaunchSeq seq(count_launches(turns, rows, K, mom ? 3 : 0) + (mom ? 1 : 0), s);
+  if (mom) {
+    const CentreDev cd{arr[0], arr[1], nullptr, nullptr, n, LTRK_F64, centre};
+    seq.push({kTimeFinalize, [cd](hipStream_t st) { return launch_centre(cd, st); }});
+  }
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
     for (int64_t j = 0; j < len; j += K) {
@@ -1294,6 +1315,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
         f.groups = groups;
         f.n = n;
         f.out = mom + c0 * 3 + p;
+        f.centre = p == 0 ? centre : nullptr;
         f.rows = static_cast<int32_t>(len);
         f.planes = 3;
         seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
@@ -1368,8 +1390,13 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
                             sizeof(uint32_t);  // a multiple of 256 B
   const size_t pot_bytes = static_cast<size_t>(ns) * sizeof(double);
   void* scratch = nullptr;
-  if ((rc = ensure_scratch(c, s, part_bytes + hist_bytes + pot_bytes, &scratch))) return rc;
+  if ((rc = ensure_scratch(c, s,
+                           part_bytes + hist_bytes + pot_bytes + kCentreDoubles * sizeof(double),
+                           &scratch)))
+    return rc;
   char* base = static_cast<char*>(scratch);
+  double* centre = mom ? reinterpret_cast<double*>(base + part_bytes + hist_bytes + pot_bytes)
+                       : nullptr;
 
   double* host = nullptr;
   void* wtab = nullptr;
@@ -1389,6 +1416,7 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
   w.pot = reinterpret_cast<double*>(base + part_bytes + hist_bytes);
   w.n_slices = ns;
   b.partials = mom ? reinterpret_cast<double*>(base) : nullptr;
+  b.centre = centre;
 
   std::string key;
   key_add(key, 7);
@@ -1403,7 +1431,11 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
   // A(t) kicks with turn t-1's potential and writes moment row t-1; row r
   // lives at r - c0 in the chunk [c0, c0 + rows) finalized once complete.
   // 2 turns + 2 launches, and a finalize after each chunk of rows.
-  LaunchSeq seq(2 * turns + 2 + (mom ? (turns + rows - 1) / rows : 0), s);
+  LaunchSeq seq(2 * turns + 2 + (mom ? (turns + rows - 1) / rows + 1 : 0), s);
+  if (mom) {
+    const CentreDev cd{z, dp, nullptr, nullptr, n, LTRK_F64, centre};
+    seq.push({kTimeFinalize, [cd](hipStream_t st) { return launch_centre(cd, st); }});
+  }
   auto turn_launch = [&](int phase, int64_t row) {
     const int32_t local = static_cast<int32_t>(row < 0 ? 0 : row % rows);
     seq.push({kTimeTrack, [b, ce, w, phase, local, block, grid, ppl](hipStream_t st) {
@@ -1419,6 +1451,7 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
       f.groups = groups;
       f.n = n;
       f.out = mom + c0;
+      f.centre = centre;
       f.rows = static_cast<int32_t>(row - c0 + 1);
       seq.push({kTimeFinalize, [f](hipStream_t st) { return launch_finalize_single(f, st); }});
     }
@@ -1471,11 +1504,15 @@ static int moments_single(const void* z, const void* dp, const void* zc, const v
   DeviceCtx& c = ctx_for(dev);
   std::lock_guard<std::mutex> lock(c.mu);
   void* scratch = nullptr;
-  if ((rc = ensure_scratch(c, s, static_cast<size_t>(5) * scratch_cols(b.waves) * sizeof(double),
-                           &scratch)))
+  const size_t part = static_cast<size_t>(5) * scratch_cols(b.waves);
+  if ((rc = ensure_scratch(c, s, (part + kCentreDoubles) * sizeof(double), &scratch)))
     return rc;
   b.partials = static_cast<double*>(scratch);
-  hipError_t e = launch_track_single(b, 0, ppl, block, s);
+  double* centre = b.partials + part;
+  b.centre = centre;
+  hipError_t e = launch_centre(CentreDev{z, dp, zc, dc, n, dtype, centre}, s);
+  if (e != hipSuccess) return fail_hip(e, "moments centre");
+  e = launch_track_single(b, 0, ppl, block, s);
   if (e != hipSuccess) return fail_hip(e, "moments launch");
   FinalizeDev f;
   std::memset(&f, 0, sizeof(f));
@@ -1485,6 +1522,7 @@ static int moments_single(const void* z, const void* dp, const void* zc, const v
   f.groups = finalize_groups(b.waves);
   f.n = n;
   f.out = out;
+  f.centre = centre;
   f.rows = 1;
   e = launch_finalize_single(f, s);
   return e == hipSuccess ? LTRK_OK : fail_hip(e, "moments finalize");
@@ -1580,9 +1618,11 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   DeviceCtx& c = ctx_for(dev);
   std::lock_guard<std::mutex> lock(c.mu);
   void* scratch = nullptr;
-  if (any_mom &&
-      (rc = ensure_scratch(c, s, static_cast<size_t>(rows) * 5 * waves_mom * sizeof(double),
-                           &scratch)))
+  // partial regions of the bunches with moments, then their centres (2 each)
+  const size_t part_doubles = static_cast<size_t>(rows) * 5 * waves_mom;
+  if (any_mom && (rc = ensure_scratch(c, s, (part_doubles + 2 * static_cast<size_t>(nb)) *
+                                                sizeof(double),
+                                      &scratch)))
     return rc;
   // Per-bunch partial regions inside the scratch.
   std::vector<FinalizeDev> fin;
@@ -1591,6 +1631,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   for (int i = 0; i < nb; ++i) {
     if (bunches[i].moments && bunches[i].n > 0) {
       bd[i].partials = static_cast<double*>(scratch) + off;
+      bd[i].centre = static_cast<double*>(scratch) + part_doubles + 2 * i;
       FinalizeDev f;
       std::memset(&f, 0, sizeof(f));
       f.partials = bd[i].partials;
@@ -1599,6 +1640,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
       f.groups = finalize_groups(bd[i].waves);
       f.n = bd[i].n;
       f.out = bunches[i].moments;
+      f.centre = bd[i].centre;
       f.rows = max_rows;
       fin.push_back(f);
       off += rows * 5 * scratch_cols(bd[i].waves);
@@ -1614,7 +1656,7 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   for (const FinalizeDev& f : fin) key_add(key, f.out);
 
   // Device tables: found with a cached graph, else uploaded now.
-  const int64_t expected = count_launches(turns, rows, K, fin.empty() ? 0 : 1);
+  const int64_t expected = count_launches(turns, rows, K, fin.empty() ? 0 : 1) + 1;
   const bool graph_ok = plan.use_graph && s &&
                         expected <= static_cast<int64_t>(max_graph_launches());
   if (graph_ok) {
@@ -1654,6 +1696,8 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   LaunchSeq seq(graph_ok ? 0 : expected, s);
   const int64_t ntiles = static_cast<int64_t>(tiles.size());
   const int nf = static_cast<int>(fin.size());
+  if (nf > 0)
+    seq.push({kTimeFinalize, [=](hipStream_t st) { return launch_centre_bunches(d_b, nb, st); }});
   for (int64_t c0 = 0; c0 < turns; c0 += rows) {
     const int64_t len = std::min(rows, turns - c0);
     for (int64_t j = 0; j < len; j += K) {

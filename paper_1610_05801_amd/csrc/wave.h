@@ -141,6 +141,38 @@ __device__ __forceinline__ void accumulate(Sums& s, double z, double d) {
   s.zd = __builtin_fma(z, d, s.zd);
 }
 
+// The centre (c_z, c_dp) of a call's moment sums (see kCentreSample).
+struct Centre {
+  double z, d;
+};
+
+__device__ __forceinline__ Centre centre_of(const double* c) {
+  return c ? Centre{c[0], c[1]} : Centre{0.0, 0.0};
+}
+
+__device__ __forceinline__ bool is_zero(const Centre& c) { return c.z == 0.0 && c.d == 0.0; }
+
+// Particle p's contribution to a lane's sums about the centre; SHIFT false
+// skips the subtractions (the centre is then (0, 0): x - 0 is x exactly, so
+// both forms give the same bits). The padding lanes past the end of a bunch
+// hold (0, 0) and add nothing to sums about (0, 0); about another centre
+// they would add -c, so in the wave tile that holds the end of the bunch
+// (TAIL) they add zeros instead.
+template <bool SHIFT, bool TAIL>
+__device__ __forceinline__ void add_particle(Sums& s, int p, double z, double d,
+                                             const Centre& c, bool live) {
+  double zs = SHIFT ? z - c.z : z;
+  double ds = SHIFT ? d - c.d : d;
+  if constexpr (SHIFT && TAIL) {
+    zs = live ? zs : 0.0;
+    ds = live ? ds : 0.0;
+  }
+  if (p == 0)
+    s = first_sums(zs, ds);
+  else
+    accumulate(s, zs, ds);
+}
+
 // Wave-scope ordering of LDS accesses (all lanes of one wave; no block barrier).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -213,10 +245,11 @@ __host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
 // to the moment sums (the single-harmonic map keeps (0, 0) fixed, so its
 // kernels skip the check; maps with RF phase offsets or momentum steps move
 // it).
-template <int INTEG, int P, bool MOM, bool TAIL, class Turn>
+template <int INTEG, int P, bool MOM, bool TAIL, bool SHIFT, class Turn>
 __device__ __forceinline__ void turn_loop(const Turn& turn, double (&z)[P], double (&d)[P],
                                           const bool (&live)[P], int turns, double* buf,
-                                          double* out, int64_t waves, int lane) {
+                                          double* out, int64_t waves, int lane,
+                                          const Centre& cen) {
   for (int t = 0; t < turns; t += kFlushTurns) {
     const int nb = turns - t < kFlushTurns ? turns - t : kFlushTurns;
     for (int j = 0; j < nb; ++j) {
@@ -227,12 +260,7 @@ __device__ __forceinline__ void turn_loop(const Turn& turn, double (&z)[P], doub
         if constexpr (INTEG != kMeasureOnly) {
           if (!TAIL || live[p]) turn(tc, z[p], d[p]);
         }
-        if constexpr (MOM) {
-          if (p == 0)
-            s = first_sums(z[0], d[0]);
-          else
-            accumulate(s, z[p], d[p]);
-        }
+        if constexpr (MOM) add_particle<SHIFT, TAIL>(s, p, z[p], d[p], cen, live[p]);
       }
       if constexpr (MOM) stage_sums(buf, j, s, lane);
     }
@@ -268,13 +296,30 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, const Exact& exact, 
     }
   }
   double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
-  if constexpr (INTEG == kMeasureOnly) {
-    turn_loop<INTEG, P, MOM, TAIL>(exact, z, d, live, turns, buf, out, b.waves, lane);
-  } else {
-    if (in_exact_range<P>(b.c, z, d, turns))
-      turn_loop<INTEG, P, MOM, TAIL>(exact, z, d, live, turns, buf, out, b.waves, lane);
+  const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
+  // the tile holding the end of the bunch masks its padding lanes out of
+  // sums about a centre (add_particle)
+  const bool tail = TAIL || (w + 1) * static_cast<int64_t>(kWave * P) > b.n;
+  auto shifted = [&](const auto& turn) {
+    if (tail)
+      turn_loop<INTEG, P, MOM, true, true>(turn, z, d, live, turns, buf, out, b.waves, lane, cen);
     else
-      turn_loop<INTEG, P, MOM, TAIL>(safe, z, d, live, turns, buf, out, b.waves, lane);
+      turn_loop<INTEG, P, MOM, TAIL, true>(turn, z, d, live, turns, buf, out, b.waves, lane, cen);
+  };
+  if constexpr (INTEG == kMeasureOnly) {
+    shifted(exact);
+  } else {
+    // The exact-product reduction with and without the centre, and the
+    // rounded-phase reduction (rare: far-escaped particles) with it.
+    if (in_exact_range<P>(b.c, z, d, turns)) {
+      if (is_zero(cen))
+        turn_loop<INTEG, P, MOM, TAIL, false>(exact, z, d, live, turns, buf, out, b.waves, lane,
+                                              cen);
+      else
+        shifted(exact);
+    } else {
+      shifted(safe);
+    }
   }
   if constexpr (INTEG != kMeasureOnly) {
 #pragma unroll

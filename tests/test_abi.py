@@ -147,8 +147,10 @@ def test_tune_cache_file_roundtrip(tmp_path):
 
 
 def test_engine_footprint():
-    assert ltrk.ltrk_engine_footprint(1000, 100) == 16128 + 4096
-    assert ltrk.ltrk_engine_footprint(10_000_000, 100_000) == 160_000_000 + 4_000_000
+    # state and moment rows rounded up to 256 B, plus 256 B for the centre of
+    # the moment sums
+    assert ltrk.ltrk_engine_footprint(1000, 100) == 16128 + 4096 + 256
+    assert ltrk.ltrk_engine_footprint(10_000_000, 100_000) == 160_000_000 + 4_000_000 + 256
 
 
 def test_rf2_validation_before_any_launch():
