@@ -1069,8 +1069,6 @@ def bench_batched(args):
     res = {"workload": "batched: %d bunches (log-uniform 1e3-1e6), %d turns" % (len(specs), T),
            "particles": total}
     for dtype in ("f64", "f32c"):
-        plan = ltrk.ltrk_autotune("leapfrog", dtype, total // len(specs) * 4, stream=stream) \
-            if args.tune else ltrk.ltrk_get_plan("leapfrog", dtype, total)
         bunches = []
         for s in specs:
             r = ring_for(s)
@@ -1084,16 +1082,31 @@ def bench_batched(args):
                 b["z"], b["dp"], b["z_comp"], b["dp_comp"] = [torch.as_tensor(a).to(dev)
                                                               for a in (zh, dh, zc, dc)]
             bunches.append(b)
-        with torch.cuda.stream(stream):
-            warm = [dict(b, moments=None) for b in bunches]
-            ltrk.ltrk_track_batched(warm, 64, "leapfrog", dtype, stream=stream)   # warm-up
-            stream.synchronize()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ltrk.ltrk_track_batched(bunches, T, "leapfrog", dtype, stream=stream)
-            stream.synchronize()
-            dt = time.perf_counter() - t0
+
+        def timed():
+            with torch.cuda.stream(stream):
+                warm = [dict(b, moments=None) for b in bunches]
+                ltrk.ltrk_track_batched(warm, 64, "leapfrog", dtype, stream=stream)   # warm-up
+                stream.synchronize()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ltrk.ltrk_track_batched(bunches, T, "leapfrog", dtype, stream=stream)
+                stream.synchronize()
+                return time.perf_counter() - t0
+
+        plan = ltrk.ltrk_get_plan_batched("leapfrog", dtype, total)
+        dt = timed()
         res[dtype] = {"particle_turns_per_s": total * T / dt, "seconds": dt, "plan": plan}
+        if args.tune:
+            # the batched launch tuned on its own tile table (probe bunches of
+            # these sizes and rings), then the same run with the tuned plan
+            t0 = time.perf_counter()
+            tuned = ltrk.ltrk_autotune_batched(bunches, "leapfrog", dtype, stream=stream)
+            tune_s = time.perf_counter() - t0
+            dt_t = timed()
+            res[dtype]["tuned"] = {"plan": tuned, "particle_turns_per_s": total * T / dt_t,
+                                   "seconds": dt_t, "tuning_seconds": tune_s,
+                                   "vs_default": dt / dt_t}
         log(dtype, json.dumps(res[dtype]))
         del bunches
         torch.cuda.empty_cache()

@@ -351,9 +351,25 @@ int ltrk_set_plan(const ltrk_plan* plan);
 int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
 
 /* Time candidate plans on scratch particles of size n (on `stream`,
- * synchronising it) and cache the fastest for (device, integrator, dtype,
- * floor(log2 n)). `best` (host, may be NULL) receives it. */
+ * synchronising it) and cache the fastest for single-bunch calls of (device,
+ * integrator, dtype, floor(log2 n)). `best` (host, may be NULL) receives it. */
 int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best);
+
+/* The plan a batched call over bunches of total_n particles would use now. */
+int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan* out);
+
+/* Tune the batched launch (the paper's sweep of turns per kernel call,
+ * section 2.3) for a bunch table like `bunches` (HOST array of nb
+ * descriptors; only each bunch's n, ring and whether it has moments are read,
+ * its arrays are not touched): probe bunches of those sizes and rings are
+ * tracked on `stream` (synchronised) with every combination of 128, 256, 512
+ * and 1024 turns per launch, 64, 128 and 256 threads per block and 2, 4 and 8
+ * particles per lane, and the fastest plan is cached for batched calls of
+ * (device, integrator, dtype, floor(log2 of the total particles)). Needs
+ * device memory for the probes' state and 4096 moment rows per bunch with
+ * moments. `best` (host, may be NULL) receives the plan. */
+int ltrk_autotune_batched(const ltrk_bunch* bunches, int nb, int integrator, int dtype,
+                          void* stream, ltrk_plan* best);
 
 /* Save / load the tuning cache as text, one entry per line: arch integrator
  * dtype log2(n) batched K block ppl graph. Loading merges the file's valid

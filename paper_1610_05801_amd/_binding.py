@@ -215,6 +215,9 @@ _SIGS = {
     "ltrk_set_plan": ([P(Plan)], ctypes.c_int),
     "ltrk_get_plan": ([ctypes.c_int, ctypes.c_int, c_i64, P(Plan)], ctypes.c_int),
     "ltrk_autotune": ([ctypes.c_int, ctypes.c_int, c_i64, c_vp, P(Plan)], ctypes.c_int),
+    "ltrk_get_plan_batched": ([ctypes.c_int, ctypes.c_int, c_i64, P(Plan)], ctypes.c_int),
+    "ltrk_autotune_batched": ([P(Bunch), ctypes.c_int, ctypes.c_int, ctypes.c_int, c_vp, P(Plan)],
+                              ctypes.c_int),
     "ltrk_tune_cache_save": ([ctypes.c_char_p], ctypes.c_int),
     "ltrk_tune_cache_load": ([ctypes.c_char_p], ctypes.c_int),
     "ltrk_timing_enable": ([ctypes.c_int], ctypes.c_int),
@@ -450,6 +453,28 @@ def ltrk_set_plan(turns_per_launch=None, block=None, ppl=None, use_graph=1):
 def ltrk_get_plan(integrator="leapfrog", dtype="f64", n=1) -> dict:
     p = Plan()
     _check(_lib.ltrk_get_plan(_integ(integrator), _dtype(dtype), int(n), ctypes.byref(p)))
+    return p.as_dict()
+
+
+def ltrk_get_plan_batched(integrator="leapfrog", dtype="f64", total_n=1) -> dict:
+    p = Plan()
+    _check(_lib.ltrk_get_plan_batched(_integ(integrator), _dtype(dtype), int(total_n),
+                                      ctypes.byref(p)))
+    return p.as_dict()
+
+
+def ltrk_autotune_batched(bunches, integrator="leapfrog", dtype="f64", stream=None) -> dict:
+    """Tune the batched launch for a table like `bunches` (dicts with n or z,
+    ring and optionally moments; only sizes, rings and whether moments are
+    asked for are used) and cache the plan for batched calls."""
+    arr = (Bunch * max(len(bunches), 1))()
+    for i, b in enumerate(bunches):
+        arr[i].n = int(b["n"]) if "n" in b else b["z"].numel()
+        arr[i].ring = Ring.of(b["ring"])
+        arr[i].moments = 1 if b.get("moments") is not None else None
+    p = Plan()
+    _check(_lib.ltrk_autotune_batched(arr, len(bunches), _integ(integrator), _dtype(dtype),
+                                      _stream(stream), ctypes.byref(p)))
     return p.as_dict()
 
 

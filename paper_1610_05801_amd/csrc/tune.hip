@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -25,6 +26,7 @@ extern "C" int ltrk_track_f64(double*, double*, int64_t, int64_t, const ltrk_rin
                               ltrk_moments*, void*);
 extern "C" int ltrk_track_f32c(float*, float*, float*, float*, int64_t, int64_t,
                                const ltrk_ring*, int, ltrk_moments*, void*);
+extern "C" int ltrk_track_batched(const ltrk_bunch*, int, int64_t, int, int, void*);
 
 namespace ltrk {
 
@@ -251,7 +253,147 @@ int autotune(int integrator, int dtype, int64_t n, hipStream_t s, ltrk_plan* bes
   {
     std::lock_guard<std::mutex> g(g_plan_mu);
     g_tuned[TuneKey(device_arch(), integrator, dtype, log2_bucket(n), 0)] = best;
-    g_tuned[TuneKey(device_arch(), integrator, dtype, log2_bucket(n), 1)] = best;
+  }
+  if (best_out) *best_out = best;
+  return LTRK_OK;
+}
+
+// Milliseconds of one batched call of `turns` turns over `table` with plan p
+// (best of two after a warm-up call that builds its launch graph), or < 0.
+double time_batched(const std::vector<ltrk_bunch>& table, int64_t turns, int integrator,
+                    int dtype, hipStream_t s, const ltrk_plan& p, int* rc_out) {
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_forced = true;
+    g_forced_plan = p;
+  }
+  auto call = [&]() {
+    return ltrk_track_batched(table.data(), static_cast<int>(table.size()), turns, integrator,
+                              dtype, s);
+  };
+  double best = -1.0;
+  int rc = call();
+  hipEvent_t a = nullptr, b = nullptr;
+  if (rc == LTRK_OK && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    for (int rep = 0; rep < 2 && rc == LTRK_OK; ++rep) {
+      hipEventRecord(a, s);
+      rc = call();
+      hipEventRecord(b, s);
+      if (hipEventSynchronize(b) != hipSuccess) {
+        rc = fail(LTRK_EDEVICE, "autotune: event synchronisation failed");
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, a, b);
+      if (rc == LTRK_OK && (best < 0.0 || ms < best)) best = ms;
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  *rc_out = rc;
+  return rc == LTRK_OK ? best : -1.0;
+}
+
+// Tune the batched launch on probe bunches of the caller's sizes and rings
+// (with moments where the caller's bunch has them): turns per launch, block
+// and particles per lane searched jointly.
+int autotune_batched(const ltrk_bunch* bunches, int nb, int integrator, int dtype, hipStream_t s,
+                     ltrk_plan* best_out) {
+  if (!valid_integrator(integrator)) return fail(LTRK_EINVAL, "unknown integrator %d", integrator);
+  if (!valid_dtype(dtype)) return fail(LTRK_EINVAL, "unknown dtype %d", dtype);
+  if (nb < 1 || nb > 65535 || !bunches) return fail(LTRK_EINVAL, "invalid bunch table");
+  int64_t total = 0;
+  int n_mom = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (bunches[i].n < 0) return fail(LTRK_EINVAL, "bunch %d: n < 0", i);
+    int rc = validate_ring(&bunches[i].ring);
+    if (rc) return fail(rc, "bunch %d: invalid ring", i);
+    total += bunches[i].n;
+    n_mom += bunches[i].moments && bunches[i].n > 0 ? 1 : 0;
+  }
+  if (total < 1 || total > (int64_t(1) << 34))
+    return fail(LTRK_EINVAL, "total particles out of range for tuning");
+  // ~2^31 particle-turns per probe call, at least two launches of the plan
+  const int64_t base_turns = std::max<int64_t>(64, std::min<int64_t>(4096, (int64_t(1) << 31) / total));
+  const size_t elem = dtype == LTRK_F64 ? 8 : 4;
+  const int narr = dtype == LTRK_F64 ? 2 : 4;
+  const size_t state_bytes = static_cast<size_t>(total) * elem * narr;
+  const size_t mom_bytes = static_cast<size_t>(n_mom) * 4096 * sizeof(ltrk_moments);
+  char* buf = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&buf), state_bytes + mom_bytes + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LTRK_ENOMEM, "autotune probe bunches");
+  }
+  std::vector<ltrk_bunch> table(nb);
+  int rc = LTRK_OK;
+  size_t off = 0;
+  int mi = 0;
+  char* mom_base = buf + ((state_bytes + 255) & ~size_t(255));
+  for (int i = 0; i < nb && rc == LTRK_OK; ++i) {
+    ltrk_bunch& t = table[i];
+    std::memset(&t, 0, sizeof(t));
+    const size_t bytes = static_cast<size_t>(bunches[i].n) * elem;
+    void* arr[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < narr; ++k) {
+      arr[k] = bunches[i].n > 0 ? buf + off : nullptr;
+      off += bytes;
+    }
+    t.z = arr[0];
+    t.dp = arr[1];
+    t.z_comp = arr[2];
+    t.dp_comp = arr[3];
+    t.n = bunches[i].n;
+    t.ring = bunches[i].ring;
+    if (bunches[i].moments && bunches[i].n > 0)
+      t.moments = reinterpret_cast<ltrk_moments*>(mom_base) + static_cast<size_t>(mi++) * 4096;
+    if (t.n > 0) {
+      hipError_t e = hipSuccess;
+      if (dtype == LTRK_F64)
+        e = launch_fill_probe(static_cast<double*>(t.z), static_cast<double*>(t.dp), t.n, s);
+      else
+        for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipMemsetAsync(arr[k], 0, bytes, s);
+      if (e != hipSuccess) rc = fail_hip(e, "autotune fill");
+    }
+  }
+  bool saved_forced;
+  ltrk_plan saved_plan;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    saved_forced = g_forced;
+    saved_plan = g_forced_plan;
+  }
+  ltrk_plan best{256, 256, 8, 1};
+  double best_rate = -1.0;
+  const int ppls[3] = {2, 4, 8};
+  const int blocks[3] = {64, 128, 256};
+  const int ks[4] = {128, 256, 512, 1024};
+  for (int ki = 0; ki < 4 && rc == LTRK_OK; ++ki) {
+    const int64_t turns = std::min<int64_t>(4096, std::max<int64_t>(base_turns, 2 * ks[ki]));
+    for (int pi = 0; pi < 3 && rc == LTRK_OK; ++pi) {
+      for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
+        const ltrk_plan p{ks[ki], blocks[bi], ppls[pi], 1};
+        const double ms = time_batched(table, turns, integrator, dtype, s, p, &rc);
+        if (ms > 0.0) {
+          const double rate = static_cast<double>(total) * turns / ms;
+          if (rate > best_rate) {
+            best_rate = rate;
+            best = p;
+          }
+        }
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_forced = saved_forced;
+    g_forced_plan = saved_plan;
+  }
+  hipStreamSynchronize(s);
+  hipFree(buf);
+  if (rc != LTRK_OK) return rc;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_tuned[TuneKey(device_arch(), integrator, dtype, log2_bucket(total), 1)] = best;
   }
   if (best_out) *best_out = best;
   return LTRK_OK;
@@ -288,10 +430,30 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out) {
   return LTRK_OK;
 }
 
+int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan* out) {
+  clear_error();
+  if (!out) return fail(LTRK_EINVAL, "out is NULL");
+  if (!valid_integrator(integrator) || !valid_dtype(dtype) || total_n < 0)
+    return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
+  *out = choose_plan(integrator, dtype, total_n, true);
+  return LTRK_OK;
+}
+
 int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best) {
   try {
     clear_error();
     return autotune(integrator, dtype, n, static_cast<hipStream_t>(stream), best);
+  } catch (...) {
+    return fail(LTRK_EDEVICE, "unexpected internal error in autotune");
+  }
+}
+
+int ltrk_autotune_batched(const ltrk_bunch* bunches, int nb, int integrator, int dtype,
+                          void* stream, ltrk_plan* best) {
+  try {
+    clear_error();
+    return autotune_batched(bunches, nb, integrator, dtype, static_cast<hipStream_t>(stream),
+                            best);
   } catch (...) {
     return fail(LTRK_EDEVICE, "unexpected internal error in autotune");
   }

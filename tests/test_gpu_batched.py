@@ -100,3 +100,39 @@ def test_batched_f32c_matches_alone(ltrk):
             assert torch.equal(x, y)
         assert torch.equal(b["moments"], m)
     ltrk.ltrk_set_plan()
+
+
+def test_autotuned_batched_plan_matches_oracle(ltrk):
+    """The batched launch tuned on its own tile table: the plan is cached for
+    batched calls of that total size (and only for them), and a batched call
+    with it matches the oracle on every bunch."""
+    specs = [(1_000, 2_000_000.0, 4620), (23_456, 5_000_000.0, 9240), (4_097, 1_000_000.0, 4620),
+             (70_001, 8_000_000.0, 9240), (515, 3_000_000.0, 4620)]
+    T = 300
+    bunches, inits = [], []
+    for k, (n, v, h) in enumerate(specs):
+        r = dict(SPS_RING, voltage_V=v, harmonic=float(h))
+        c = oracle.derive(r)
+        z0, dp0 = gaussian_bunch(n, 1e-3 * c["D"] / c["omega"], 1e-3, 300 + k)
+        inits.append((z0, dp0, r))
+        bunches.append(dict(z=dev(z0), dp=dev(dp0), ring=r,
+                            moments=torch.empty((T, 5), dtype=torch.float64, device="cuda")))
+    total = sum(n for n, _v, _h in specs)
+    stream = torch.cuda.Stream()
+    tuned = ltrk.ltrk_autotune_batched(bunches, "ruth4", "f64", stream=stream)
+    assert tuned["turns_per_launch"] in (128, 256, 512, 1024)
+    assert tuned["block"] in (64, 128, 256) and tuned["ppl"] in (2, 4, 8)
+    assert ltrk.ltrk_get_plan_batched("ruth4", "f64", total) == tuned
+    # the probe bunches left the caller's arrays alone
+    assert np.array_equal(bunches[0]["z"].cpu().numpy(), inits[0][0])
+    with torch.cuda.stream(stream):
+        ltrk.ltrk_track_batched(bunches, T, "ruth4", "f64", stream=stream)
+    torch.cuda.synchronize()
+    for (z0, dp0, r), b in zip(inits, bunches):
+        zr, dr, mr = oracle.track(z0, dp0, T, r, "ruth4")
+        e = bucket_error(b["z"].cpu().numpy(), b["dp"].cpu().numpy(), zr, dr, r)
+        near = near_separatrix(z0, dp0, r)
+        assert e[~near].max() <= 1e-12
+        if near.any():
+            assert e[near].max() <= 1e-10
+        assert moment_error(b["moments"].cpu().numpy(), mr).max() <= 1e-10
