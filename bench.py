@@ -560,9 +560,9 @@ def bench_ksweep(args):
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
     rows = []
     base = ltrk.ltrk_get_plan("leapfrog", "f64", n)
-    for ppl in (2, 4, 8):
-        for K in (1, 8, 16, 32, 64, 128, 256, 512):
-            for graph in (0, 1):
+    for ppl in args.ppls:
+        for K in args.ks:
+            for graph in args.graphs:
                 ltrk.ltrk_set_plan(K, base["block"], ppl, graph)
                 z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
                 mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
@@ -576,6 +576,7 @@ def bench_ksweep(args):
                     dt = time.perf_counter() - t0
                 row = {"K": K, "ppl": ppl, "graph": graph, "block": base["block"],
                        "particle_turns_per_s": n * T / dt}
+                del z, dp, mom
                 rows.append(row)
                 log(json.dumps(row))
     ltrk.ltrk_set_plan()
@@ -1056,6 +1057,18 @@ def _matched_sigma_z(ltrk, ring, sigma_dp):
     return sigma_dp * d["slip_length"] / d["omega_s"]
 
 
+def _moment_rel_error(m, ref):
+    """Per-row errors of moment rows against reference rows: means over the
+    reference rms, rms and emittance relative."""
+    m, ref = np.asarray(m), np.asarray(ref)
+    err = np.empty_like(ref)
+    err[:, 0] = np.abs(m[:, 0] - ref[:, 0]) / ref[:, 1]
+    err[:, 2] = np.abs(m[:, 2] - ref[:, 2]) / ref[:, 3]
+    for j in (1, 3, 4):
+        err[:, j] = np.abs(m[:, j] - ref[:, j]) / np.abs(ref[:, j])
+    return err
+
+
 def bench_batched(args):
     import torch
     import paper_1610_05801_amd as ltrk
@@ -1097,6 +1110,19 @@ def bench_batched(args):
         plan = ltrk.ltrk_get_plan_batched("leapfrog", dtype, total)
         dt = timed()
         res[dtype] = {"particle_turns_per_s": total * T / dt, "seconds": dt, "plan": plan}
+        moms = [b["moments"].cpu().numpy() for b in bunches]
+        if dtype == "f64":
+            f64_moms = moms
+        else:
+            # F32C against FP64, per bunch and over all turns: means scaled by
+            # their rms, rms and emittance relative
+            worst = np.zeros(5)
+            for a, b in zip(moms, f64_moms):
+                worst = np.maximum(worst, _moment_rel_error(a, b).max(axis=0))
+            res[dtype]["error_vs_f64"] = dict(zip(
+                ("mean_z_over_rms", "rms_z", "mean_dp_over_rms", "rms_dp", "emit_rms"),
+                worst.tolist()), note="max over bunches and turns of the F32C moments against "
+                "the FP64 run of the same bunches")
         if args.tune:
             # the batched launch tuned on its own tile table (probe bunches of
             # these sizes and rings), then the same run with the tuned plan
@@ -1171,7 +1197,39 @@ def bench_serving(args):
         row = dict(run(arrivals), load=frac, rate_req_per_s=lam)
         out["rows"].append(row)
         log(json.dumps(row))
+    out["f32c_error_vs_f64"] = _serving_f32c_error(ltrk, torch, specs, states, rings)
     print(json.dumps(out), flush=True)
+
+
+def _serving_f32c_error(ltrk, torch, specs, states, rings, max_work=2e10, max_jobs=24):
+    """F32C accuracy on the serving mix: F32C requests (the first max_jobs of
+    at most max_work particle-turns, so the check stays short; a job's result
+    in the engine equals its standalone run) tracked alone in F32C and in
+    FP64 from the same initial state; max over turns of the moment errors."""
+    from synth import join_f32c
+    dev = torch.device("cuda:0")
+    per = {}
+    picked = [sp for sp in specs if sp.dtype == "f32c" and sp.n * sp.turns <= max_work][:max_jobs]
+    for sp in picked:
+        zh, dh, zc, dc = states[sp.rid]
+        t32 = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
+        t64 = [torch.as_tensor(join_f32c(zh, zc)).to(dev), torch.as_tensor(join_f32c(dh, dc)).to(dev)]
+        m32 = torch.empty((sp.turns, 5), dtype=torch.float64, device=dev)
+        m64 = torch.empty_like(m32)
+        ltrk.ltrk_track_f32c(*t32, sp.turns, rings[sp.rid], sp.integrator, m32)
+        ltrk.ltrk_track_f64(*t64, sp.turns, rings[sp.rid], sp.integrator, m64)
+        torch.cuda.synchronize()
+        err = _moment_rel_error(m32.cpu().numpy(), m64.cpu().numpy()).max(axis=0)
+        per.setdefault(sp.integrator, []).append(err)
+    out = {"jobs": len(picked), "max_work_particle_turns": max_work,
+           "note": "max over turns; means over the rms; per integrator: max and median over jobs"}
+    for integ, errs in per.items():
+        e = np.array(errs)
+        out[integ] = {"jobs": len(errs), "max": dict(zip(
+            ("mean_z_over_rms", "rms_z", "mean_dp_over_rms", "rms_dp", "emit_rms"),
+            e.max(axis=0).tolist())), "median_rms_z": float(np.median(e[:, 1])),
+            "median_rms_dp": float(np.median(e[:, 3]))}
+    return out
 
 
 COUNTER_CAL_BYTES = 1 << 29   # 512 MiB read + 512 MiB written by the calibration kernel
@@ -1212,6 +1270,44 @@ def bench_counters(args):
     ltrk.ltrk_set_plan()
     print(json.dumps({"workload": "counters", "fused_plan": plan,
                       "calibration_bytes": COUNTER_CAL_BYTES}), flush=True)
+
+
+def summarize_valu(csv_path, out_path, turns_per_launch):
+    """Condense a rocprofv3 --pmc CSV of the SQ_INSTS_VALU* counters of
+    --workload counters into a per-launch table (instructions per
+    particle-turn, executed FP64 flops, clock, issue utilisation)."""
+    import csv
+    rows = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if "k_track_single" not in r["Kernel_Name"]:
+                continue
+            d = rows.setdefault(int(r["Dispatch_Id"]), {
+                "kernel": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = ["| Launch | Kernel | Duration [us] | VALU instr / pt | FP64 FMA / pt | FP64 ADD / pt | "
+           "FP64 MUL / pt | executed FP64 flop / pt | clock [GHz] | VALU issue util |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for i, (_, d) in enumerate(sorted(rows.items())):
+        fused = "<1, 0, 8>" in d["kernel"]
+        # fused: 1e6 particles x K turns; unfused: 1e8 particles x 1 turn
+        pt = 1_000_000 * turns_per_launch if fused else 100_000_000
+        per = {k: d.get(k, 0.0) * 64 / pt for k in ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64",
+                                                      "SQ_INSTS_VALU_ADD_F64",
+                                                      "SQ_INSTS_VALU_MUL_F64")}
+        cycles = d.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        secs = d["ns"] * 1e-9
+        out.append("| %d | %s | %.1f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+            i, "fused" if fused else "unfused", d["ns"] / 1e3, per["SQ_INSTS_VALU"],
+            per["SQ_INSTS_VALU_FMA_F64"], per["SQ_INSTS_VALU_ADD_F64"],
+            per["SQ_INSTS_VALU_MUL_F64"],
+            2 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_ADD_F64"] +
+            per["SQ_INSTS_VALU_MUL_F64"], cycles / secs / 1e9 if secs else 0.0,
+            d.get("SQ_INSTS_VALU", 0.0) / (256 * cycles) if cycles else 0.0))
+    with open(out_path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
 
 
 def summarize_counters(fetch_csv, write_csv, out_path, turns_per_launch):
@@ -1276,6 +1372,12 @@ def main():
     ap.add_argument("--sweep-turns", type=int, default=1_000_000,
                     help="turns of every row of --workload nsweep (the paper's table: 1e6)")
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
+    ap.add_argument("--ks", type=int, nargs="+", default=[1, 8, 16, 32, 64, 128, 256, 512],
+                    help="turns per launch of --workload ksweep")
+    ap.add_argument("--ppls", type=int, nargs="+", default=[2, 4, 8],
+                    help="particles per lane of --workload ksweep")
+    ap.add_argument("--graphs", type=int, nargs="+", default=[0, 1],
+                    help="graph replay off/on of --workload ksweep")
     ap.add_argument("--quick", action="store_true", help="skip the FP32 and unfused legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -1286,6 +1388,8 @@ def main():
     ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8, 1.0])
     ap.add_argument("--summarize", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "K"),
                     help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
+    ap.add_argument("--summarize-valu", nargs=3, metavar=("VALU_CSV", "OUT", "K"),
+                    help="condense a rocprofv3 SQ_INSTS_VALU* CSV into a markdown table")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: libltrk has no multi-GPU path "
@@ -1295,6 +1399,9 @@ def main():
     if args.summarize:
         summarize_counters(args.summarize[0], args.summarize[1], args.summarize[2],
                            int(args.summarize[3]))
+        return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu[0], args.summarize_valu[1], int(args.summarize_valu[2]))
         return
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,

@@ -179,7 +179,9 @@ __device__ __forceinline__ void wave_f32c(const BunchDev& b, int64_t w, int turn
       dc[p] = __builtin_nontemporal_load(&dcp[i]);
     }
   }
-  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves +
+                           partial_col(w, b.waves)
+                     : nullptr;
   const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
   bool live[P];
 #pragma unroll

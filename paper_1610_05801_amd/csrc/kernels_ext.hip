@@ -84,7 +84,9 @@ __device__ __forceinline__ void wave_ext(const BunchDev& b, const Turn& turn, in
       d[p] = __builtin_nontemporal_load(&dpp[i]);
     }
   }
-  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves +
+                           partial_col(w, b.waves)
+                     : nullptr;
   const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
   auto loop = [&](auto shift) {
     constexpr bool SHIFT = decltype(shift)::value;
@@ -193,7 +195,9 @@ __device__ __forceinline__ void wave_6d(const Bunch6Dev& b, const Coeffs6d& c, i
     for (int k = 0; k < 6; ++k) s6[k][p] = i < b.n ? __builtin_nontemporal_load(&arr[k][i]) : 0.0;
   }
   const Rf2Src src{c.rf};
-  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 15 * b.waves + w : nullptr;
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 15 * b.waves +
+                           partial_col(w, b.waves)
+                     : nullptr;
   // the (z, dp) sums about the call's centre (the transverse centroids turn
   // with the betatron phase, so no fixed centre follows them: theirs is 0)
   const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};

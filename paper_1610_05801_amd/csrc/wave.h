@@ -227,6 +227,25 @@ __device__ __forceinline__ void flush_rows(const double* buf, int rows, double* 
   if (part == 0 && row < rows) out[static_cast<int64_t>(row) * stride] = x;
 }
 
+// Column of wave tile w in a row of per-wave partial sums (W tiles). A
+// flush writes one double per (turn, moment) into the wave's column, so the
+// 16 columns of a 128-B line are written by 16 different waves; with
+// columns in wave order those came from four blocks on four XCDs (blocks go
+// to the 8 XCDs in turn), each XCD's L2 holding and writing back a partial
+// line. Columns are therefore dealt so that a line's 16 waves belong to
+// blocks of 4 waves on one XCD: in each group of 128 tiles, tile r = 4b + i
+// (block b = 8s + x of the group, wave i) takes column 16x + 4s + i. The
+// order depends on w and W only (the finalize adds columns 0, 1, ... in
+// order), so results stay the same for every launch shape; the last partial
+// group keeps wave order.
+__host__ __device__ __forceinline__ int64_t partial_col(int64_t w, int64_t W) {
+  const int64_t full = W & ~int64_t(127);
+  if (w >= full) return w;
+  const int r = static_cast<int>(w & 127);
+  const int b = r >> 2, i = r & 3;
+  return (w - r) + ((b & 7) << 4) + ((b >> 3) << 2) + i;
+}
+
 // LDS doubles per wave for a launch of `turns` turns (the row buffer holds at
 // most kFlushTurns turns of 5 sums).
 __host__ __device__ __forceinline__ int lds_doubles_per_wave(int turns) {
@@ -295,7 +314,9 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, const Exact& exact, 
       d[p] = __builtin_nontemporal_load(&dpp[i]);
     }
   }
-  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves + w : nullptr;
+  double* out = MOM ? b.partials + static_cast<int64_t>(row0) * 5 * b.waves +
+                           partial_col(w, b.waves)
+                     : nullptr;
   const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
   // the tile holding the end of the bunch masks its padding lanes out of
   // sums about a centre (add_particle)
