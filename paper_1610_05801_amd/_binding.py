@@ -12,7 +12,10 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# LTRK_LIBRARY may name another build of the same library (kernel variants).
+# LTRK_LIBRARY may name another build of this same library to load instead of
+# the in-tree one (a development and testing override, e.g. to time a kernel
+# change against the committed build in one process); unset, the in-tree
+# build is the one that runs.
 LIB_PATH = os.environ.get("LTRK_LIBRARY") or os.path.join(HERE, "libltrk.so")
 
 if not os.path.exists(LIB_PATH):

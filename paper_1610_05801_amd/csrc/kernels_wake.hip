@@ -11,10 +11,12 @@
 //                    block's LDS slice histogram, then adds the non-zero bins
 //                    into its copy of the global slice counts (integer adds,
 //                    so the counts do not depend on the order of the blocks);
-//   k_wake_potential one block adds the copies of the counts into LDS (and
-//                    zeroes them for the next turn) and forms the causal potential
-//                    V_k = sum_{j >= k} count_j W_{j-k}, each sum split into
-//                    up to 4 consecutive j ranges added in range order.
+//   k_wake_potential blocks of 32 slices add the copies of the counts into
+//                    LDS and form the causal potential V_k = sum_{j >= k}
+//                    count_j W_{j-k}, each sum split into 8 consecutive j
+//                    ranges added in range order; two count buffers alternate
+//                    from turn to turn, so these blocks also zero the other
+//                    one for the next map step.
 // k_wake_turn runs a grid-stride loop over wave tiles on a fixed grid, so a
 // wave's tiles, and with them its moment sums, do not depend on timing.
 // The state moves 32 B per particle-turn through HBM: the bound is HBM.
@@ -147,51 +149,53 @@ __global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c
 }
 
 // The causal potential V_k = sum_{j >= k} count_j W_{j-k} from the slice
-// counts (the copies added and staged in LDS), which are then zeroed for the
-// next turn; one block.
-// The sum of slice k is split into `parts` consecutive j ranges added by
-// neighbouring threads, whose partial sums are then added in range order.
-// The wake table is staged in LDS when it fits beside the counts.
+// counts of w.counts (the copies added and staged in LDS); the block of
+// slices [k0, k0 + kWakePotSlices) needs the counts of slices k0 and up.
+// Each slice's sum is split into 8 consecutive j ranges added by neighbouring
+// threads, whose partial sums are then added in range order. The blocks also
+// zero w.clear (the other parity's counts) for the next map step: nothing
+// reads or writes that buffer while this kernel runs. The wake table is
+// staged in LDS when it fits beside the counts.
 __global__ __launch_bounds__(kWakePotThreads) void k_wake_potential(WakeDev w) {
   extern __shared__ double sh[];
+  constexpr int kParts = kWakePotThreads / kWakePotSlices;  // 8
   const int ns = w.n_slices;
+  const int k0 = static_cast<int>(blockIdx.x) * kWakePotSlices;
+  const int m = ns - k0;                        // counts and lags this block needs
   const bool stage_w = ns <= kWakeStageSlices;
-  double* cnt = sh;                           // n_slices
-  double* part = sh + ns;                     // kWakePotThreads
-  double* wl = part + kWakePotThreads;        // n_slices when staged
+  double* cnt = sh;                             // counts of slices k0 .. ns - 1
+  double* part = sh + m;                        // kWakePotThreads partial sums
+  double* wl = part + kWakePotThreads;          // lags 0 .. m - 1 when staged
   const int stride = kWakeCountStride(ns);
-  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
     uint64_t total = 0;
 #pragma unroll
-    for (int c = 0; c < kWakeCountCopies; ++c) {
-      total += w.counts[c * stride + k];
-      w.counts[c * stride + k] = 0u;
-    }
-    cnt[k] = static_cast<double>(total);
-    if (stage_w) wl[k] = w.wtab[k];
+    for (int c = 0; c < kWakeCountCopies; ++c) total += w.counts[c * stride + k0 + i];
+    cnt[i] = static_cast<double>(total);
+    if (stage_w) wl[i] = w.wtab[i];
   }
+  const int n_clear = kWakeCountCopies * stride;
+  for (int i = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_clear;
+       i += gridDim.x * blockDim.x)
+    w.clear[i] = 0u;
   __syncthreads();
   const double* __restrict__ wt = stage_w ? wl : w.wtab;
-  const int parts = ns <= kWakePotThreads / 4 ? 4 : ns <= kWakePotThreads / 2 ? 2 : 1;
-  const int per_pass = kWakePotThreads / parts;
-  for (int k0 = 0; k0 < ns; k0 += per_pass) {
-    const int k = k0 + static_cast<int>(threadIdx.x) / parts;
-    const int q = static_cast<int>(threadIdx.x) % parts;
-    double v = 0.0;
-    if (k < ns) {
-      const int len = (ns - k + parts - 1) / parts;
-      const int j0 = k + q * len;
-      const int j1 = j0 + len < ns ? j0 + len : ns;
-      for (int j = j0; j < j1; ++j) v = v + cnt[j] * wt[j - k];
-    }
-    part[threadIdx.x] = v;
-    __syncthreads();
-    if (k < ns && q == 0) {
-      double sum = part[threadIdx.x];
-      for (int r = 1; r < parts; ++r) sum = sum + part[threadIdx.x + r];
-      w.pot[k] = sum;
-    }
-    __syncthreads();
+  const int k = k0 + static_cast<int>(threadIdx.x) / kParts;   // this thread's slice
+  const int q = static_cast<int>(threadIdx.x) % kParts;
+  double v = 0.0;
+  if (k < ns) {
+    const int len = (ns - k + kParts - 1) / kParts;
+    const int j0 = k + q * len;
+    const int j1 = j0 + len < ns ? j0 + len : ns;
+    for (int j = j0; j < j1; ++j) v = v + cnt[j - k0] * wt[j - k];
+  }
+  part[threadIdx.x] = v;
+  __syncthreads();
+  if (k < ns && q == 0) {
+    double sum = part[threadIdx.x];
+#pragma unroll
+    for (int r = 1; r < kParts; ++r) sum = sum + part[threadIdx.x + r];
+    w.pot[k] = sum;
   }
 }
 
@@ -249,17 +253,20 @@ hipError_t launch_wake_turn(const BunchDev& b, const CoeffsRf2& c, const WakeDev
 }
 
 hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s) {
-  if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
+  if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices || !w.clear) return hipErrorInvalidValue;
+  const int blocks = (w.n_slices + kWakePotSlices - 1) / kWakePotSlices;
+  // LDS for the block that needs the most: counts and lags of every slice
   const size_t doubles = static_cast<size_t>(w.n_slices) + kWakePotThreads +
                         (w.n_slices <= kWakeStageSlices ? w.n_slices : 0);
-  hipLaunchKernelGGL(k_wake_potential, dim3(1), dim3(kWakePotThreads), doubles * sizeof(double),
-                     s, w);
+  hipLaunchKernelGGL(k_wake_potential, dim3(blocks), dim3(kWakePotThreads),
+                     doubles * sizeof(double), s, w);
   return hipGetLastError();
 }
 
 hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s) {
   if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
-  const int n = kWakeCountCopies * kWakeCountStride(w.n_slices);
+  // both parities' buffers (w.counts is the first of the two)
+  const int n = 2 * kWakeCountCopies * kWakeCountStride(w.n_slices);
   hipLaunchKernelGGL(k_wake_zero, dim3((n + 255) / 256), dim3(256), 0, s, w.counts, n);
   return hipGetLastError();
 }

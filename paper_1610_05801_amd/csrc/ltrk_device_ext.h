@@ -80,7 +80,8 @@ __host__ __device__ inline int lds_doubles_per_wave_6d(int turns) {
 // map step and the potential at the slice centres.
 constexpr int kWakeMaxSlices = 4096;
 constexpr int kWakeMaxBlocks = 1024;
-constexpr int kWakePotThreads = 1024;   // block of the potential kernel
+constexpr int kWakePotThreads = 256;    // block of the potential kernel
+constexpr int kWakePotSlices = 32;      // slices whose potential one block forms
 constexpr int kWakeStageSlices = 2048;  // wake table staged in LDS up to this many slices
 // The global slice counts are held in kWakeCountCopies copies, kWakeCountStride(n)
 // counters apart; block b adds into copy b % kWakeCountCopies, which spreads
@@ -93,7 +94,10 @@ struct WakeDev {
   double dz;
   double kappa;          // q Q_mp / (beta p0 c): delta kick per volt of potential
   const double* wtab;    // [n_slices] W(m dz / (beta c)), W(0) half the limit
-  uint32_t* counts;      // [kWakeCountCopies][stride] counts of the last map step (zero between turns)
+  uint32_t* counts;      // [kWakeCountCopies][stride] counts of the last map step: the
+                         // buffer of this turn's parity (two alternate, turn by turn)
+  uint32_t* clear;       // the other parity's buffer: the potential kernel zeroes it
+                         // for the next map step
   double* pot;           // [n_slices] potential of the last counts
   int32_t n_slices;
   int32_t pad;

@@ -1386,8 +1386,10 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
     if (rows < 1) return fail(LTRK_ENOMEM, "scratch cap too small for %lld waves", (long long)gwaves);
   }
   const size_t part_bytes = mom ? static_cast<size_t>(rows) * 5 * cols * sizeof(double) : 0;
-  const size_t hist_bytes = static_cast<size_t>(kWakeCountCopies) * kWakeCountStride(ns) *
-                            sizeof(uint32_t);  // a multiple of 256 B
+  // two parities' count buffers (turns alternate), each a multiple of 256 B
+  const size_t hist_half = static_cast<size_t>(kWakeCountCopies) * kWakeCountStride(ns) *
+                           sizeof(uint32_t);
+  const size_t hist_bytes = 2 * hist_half;
   const size_t pot_bytes = static_cast<size_t>(ns) * sizeof(double);
   void* scratch = nullptr;
   if ((rc = ensure_scratch(c, s,
@@ -1413,6 +1415,7 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
   w.kappa = rf->ring.charge_e * q_mp / (d.beta * rf->ring.p0c_eV);
   w.wtab = static_cast<const double*>(wtab);
   w.counts = reinterpret_cast<uint32_t*>(base + part_bytes);
+  w.clear = reinterpret_cast<uint32_t*>(base + part_bytes + hist_half);
   w.pot = reinterpret_cast<double*>(base + part_bytes + hist_bytes);
   w.n_slices = ns;
   b.partials = mom ? reinterpret_cast<double*>(base) : nullptr;
@@ -1436,10 +1439,19 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
     const CentreDev cd{z, dp, nullptr, nullptr, n, LTRK_F64, centre};
     seq.push({kTimeFinalize, [cd](hipStream_t st) { return launch_centre(cd, st); }});
   }
+  // Turn launch i bins into the counts of parity i % 2; potential i reads them
+  // and zeroes the other parity's, which launch i + 1 then bins into.
+  auto parity_of = [&](int64_t i) {
+    WakeDev wi = w;
+    if (i % 2) std::swap(wi.counts, wi.clear);
+    return wi;
+  };
+  int64_t launch_i = 0;
   auto turn_launch = [&](int phase, int64_t row) {
     const int32_t local = static_cast<int32_t>(row < 0 ? 0 : row % rows);
-    seq.push({kTimeTrack, [b, ce, w, phase, local, block, grid, ppl](hipStream_t st) {
-                     return launch_wake_turn(b, ce, w, phase, local, ppl, block, grid, st);
+    const WakeDev wi = parity_of(launch_i);
+    seq.push({kTimeTrack, [b, ce, wi, phase, local, block, grid, ppl](hipStream_t st) {
+                     return launch_wake_turn(b, ce, wi, phase, local, ppl, block, grid, st);
                    }});
     if (mom && row >= 0 && (row % rows == rows - 1 || row == turns - 1)) {
       const int64_t c0 = row - row % rows;
@@ -1457,7 +1469,9 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
     }
   };
   auto potential = [&]() {
-    seq.push({kTimeFinalize, [w](hipStream_t st) { return launch_wake_potential(w, st); }});
+    const WakeDev wi = parity_of(launch_i);
+    seq.push({kTimeFinalize, [wi](hipStream_t st) { return launch_wake_potential(wi, st); }});
+    ++launch_i;
   };
   seq.push({kTimeFinalize, [w](hipStream_t st) { return launch_wake_zero(w, st); }});
   turn_launch(0, -1);
