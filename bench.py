@@ -876,10 +876,10 @@ def bench_6d(args):
 
 
 def bench_wake(args):
-    """Wake kick: 10^6 and 10^7 particles x 1000 turns (leap-frog, resonator,
-    256 slices), two launches per turn. The turn kernel streams the state once
-    per turn (32 B per particle-turn: the HBM roofline); the potential kernel
-    is one block. The rate is that of an untimed replay of the call's launch
+    """Wake kick: 10^6, 10^7 and 10^8 particles (--wake-sizes) x 1000 turns
+    (leap-frog, resonator, 256 slices), two launches per turn. The turn kernel
+    streams the state once per turn (32 B per particle-turn: the HBM
+    roofline); the potential kernel runs blocks of 32 slices. The rate is that of an untimed replay of the call's launch
     graph; kernel times come from HIP events in a replay of its timed graph
     (each graph built by a warm-up call first)."""
     import torch
@@ -892,9 +892,10 @@ def bench_wake(args):
               eta2=0.0)
     mom = torch.empty((T, 5), dtype=torch.float64, device=dev)
     rows = []
-    for n in (1_000_000, 10_000_000):
+    for n in args.wake_sizes:
         z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, SEEDS["paper_scale"])
         z, dp = torch.as_tensor(z0).to(dev), torch.as_tensor(dp0).to(dev)
+        del z0, dp0
         call = lambda: ltrk.ltrk_track_wake_f64(z, dp, T, rf, SPS_WAKE, "leapfrog", mom,
                                                 stream=stream)
         with torch.cuda.stream(stream):
@@ -921,6 +922,8 @@ def bench_wake(args):
                "bytes_per_particle_turn": 2 * STATE_BYTES_PER_PARTICLE}
         rows.append(row)
         log(json.dumps(row))
+        del z, dp
+        torch.cuda.empty_cache()
     print(json.dumps({"workload": "wake kick: leap-frog, resonator (%g ohm, %g Hz, Q %g), "
                       "%d slices, 1000 turns" % (SPS_WAKE["shunt"], SPS_WAKE["freq_hz"],
                                                  SPS_WAKE["quality"], SPS_WAKE["n_slices"]),
@@ -1369,6 +1372,9 @@ def main():
                              "wake", "latency", "nsweep"])
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--turns", type=int, default=10_000)
+    ap.add_argument("--wake-sizes", type=int, nargs="+",
+                    default=[1_000_000, 10_000_000, 100_000_000],
+                    help="particles of the rows of --workload wake")
     ap.add_argument("--sweep-turns", type=int, default=1_000_000,
                     help="turns of every row of --workload nsweep (the paper's table: 1e6)")
     ap.add_argument("--tune", action="store_true", help="autotune the plan before timing")
