@@ -131,7 +131,7 @@ int ltrk_derive(const ltrk_ring* ring, ltrk_derived* out);
  * moments: device array of `turns` rows or NULL; row t receives the moments
  *   after turn t+1 (turn-0 moments: ltrk_moments_f64). The sums behind them
  *   are taken about a centre fixed for the call (the mean of an evenly
- *   strided sample of up to 4096 particles of the initial state where it
+ *   strided sample of up to 1024 particles of the initial state where it
  *   lies more than 4 sample rms from zero, else zero), so a bunch far from
  *   the origin keeps its accuracy; a centroid that moves by A rms away from
  *   that centre during the call loses about (A^2) ulp of the variance.

@@ -453,33 +453,58 @@ __device__ __forceinline__ double block_sum4(double x, double* red) {
 // Mean and variance of an evenly strided sample of S = min(n, kCentreSample)
 // particles (sample k is particle floor(k n / S)), two-pass; the centre is the
 // sample mean where it lies more than kCentreRatio sample rms from zero, else
-// 0 (also for a sample without spread, or a non-finite one).
+// 0 (also for a sample without spread, or a non-finite one). Every thread
+// loads all of its samples before the first is used (lanes past S load
+// particle 0 and are masked out of the sums), so the loads overlap.
 __device__ void centre_block(const CentreDev& c) {
   __shared__ double red[4];
   constexpr int kPer = kCentreSample / 256;
   const int64_t S = c.n < kCentreSample ? c.n : kCentreSample;
+  // floor(k n / S) = k q + floor(k r / S) with n = q S + r; k r < S^2 <= 2^20
+  const int64_t q = c.n / S;
+  const uint32_t r = static_cast<uint32_t>(c.n - q * S);
+  const uint32_t s32 = static_cast<uint32_t>(S);
+  int64_t idx[kPer];
+  bool ok[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t k = threadIdx.x + 256u * j;
+    ok[j] = k < s32;
+    idx[j] = ok[j] ? static_cast<int64_t>(k) * q + (k * r) / s32 : 0;
+  }
   double zv[kPer], dv[kPer];
+  if (c.dtype == kF64) {
+    const double* z = static_cast<const double*>(c.z);
+    const double* d = static_cast<const double*>(c.dp);
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      zv[j] = z[idx[j]];
+      dv[j] = d[idx[j]];
+    }
+  } else {
+    const float* zh = static_cast<const float*>(c.z);
+    const float* zc = static_cast<const float*>(c.z_comp);
+    const float* dh = static_cast<const float*>(c.dp);
+    const float* dc = static_cast<const float*>(c.dp_comp);
+    float a[kPer], b[kPer], e[kPer], f[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      a[j] = zh[idx[j]];
+      b[j] = zc[idx[j]];
+      e[j] = dh[idx[j]];
+      f[j] = dc[idx[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      zv[j] = static_cast<double>(a[j]) - static_cast<double>(b[j]);
+      dv[j] = static_cast<double>(e[j]) - static_cast<double>(f[j]);
+    }
+  }
   double sz = 0.0, sd = 0.0;
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
-    const int64_t k = threadIdx.x + 256 * j;
-    zv[j] = 0.0;
-    dv[j] = 0.0;
-    if (k < S) {
-      // floor(k n / S) without overflow: n = q S + r, k r < S^2
-      const int64_t i = k * (c.n / S) + (k * (c.n % S)) / S;
-      if (c.dtype == kF64) {
-        zv[j] = static_cast<const double*>(c.z)[i];
-        dv[j] = static_cast<const double*>(c.dp)[i];
-      } else {
-        zv[j] = static_cast<double>(static_cast<const float*>(c.z)[i]) -
-                static_cast<double>(static_cast<const float*>(c.z_comp)[i]);
-        dv[j] = static_cast<double>(static_cast<const float*>(c.dp)[i]) -
-                static_cast<double>(static_cast<const float*>(c.dp_comp)[i]);
-      }
-      sz += zv[j];
-      sd += dv[j];
-    }
+    sz += ok[j] ? zv[j] : 0.0;
+    sd += ok[j] ? dv[j] : 0.0;
   }
   const double Sd = static_cast<double>(S);
   const double mz = block_sum4(sz, red) / Sd;
@@ -487,7 +512,7 @@ __device__ void centre_block(const CentreDev& c) {
   double qz = 0.0, qd = 0.0;
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
-    if (threadIdx.x + 256 * j < S) {
+    if (ok[j]) {
       qz = __builtin_fma(zv[j] - mz, zv[j] - mz, qz);
       qd = __builtin_fma(dv[j] - md, dv[j] - md, qd);
     }

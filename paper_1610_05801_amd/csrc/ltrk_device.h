@@ -83,7 +83,7 @@ struct TileDev {
 // of the call's initial state (k_centre), used where it lies more than
 // kCentreRatio sample rms from zero and (0, 0) elsewhere. A wave whose
 // centre is (0, 0) runs the loop without the two subtractions.
-constexpr int kCentreSample = 4096;
+constexpr int kCentreSample = 1024;
 constexpr double kCentreRatio = 4.0;
 constexpr int kCentreDoubles = 32;  // scratch doubles reserved per centre (256 B)
 
