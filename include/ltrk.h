@@ -351,8 +351,11 @@ int ltrk_set_plan(const ltrk_plan* plan);
 int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
 
 /* Time candidate plans on scratch particles of size n (on `stream`,
- * synchronising it) and cache the fastest for single-bunch calls of (device,
- * integrator, dtype, floor(log2 n)). `best` (host, may be NULL) receives it. */
+ * synchronising it): every combination of 32, 128, 256, 512, 1024 and 2048
+ * turns per launch, 64, 128 and 256 threads per block and 1, 2, 4 and 8
+ * particles per lane, with moments. Cache the fastest for single-bunch calls
+ * of (device, integrator, dtype, floor(log2 n)). `best` (host, may be NULL)
+ * receives it. */
 int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best);
 
 /* The plan a batched call over bunches of total_n particles would use now. */

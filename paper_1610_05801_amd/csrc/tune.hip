@@ -209,34 +209,26 @@ int autotune(int integrator, int dtype, int64_t n, hipStream_t s, ltrk_plan* bes
     saved_forced = g_forced;
     saved_plan = g_forced_plan;
   }
+  // Turns per launch, block and particles per lane searched jointly; every
+  // probe call runs at least two launches of its plan.
   ltrk_plan best{128, 256, 4, 1};
   double best_rate = -1.0;
   const int ppls[4] = {1, 2, 4, 8};
   const int blocks[3] = {64, 128, 256};
-  for (int pi = 0; pi < 4 && rc == LTRK_OK; ++pi) {
-    for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
-      ltrk_plan p{128, blocks[bi], ppls[pi], 1};
-      const double ms = time_call(integrator, dtype, n, turns, arrays, mom, s, ring, p, &rc);
-      if (ms > 0.0) {
-        const double rate = static_cast<double>(n) * turns / ms;
-        if (rate > best_rate) {
-          best_rate = rate;
-          best = p;
+  const int ks[6] = {32, 128, 256, 512, 1024, 2048};
+  for (int ki = 0; ki < 6 && rc == LTRK_OK; ++ki) {
+    const int64_t t = std::min<int64_t>(4096, std::max<int64_t>(turns, 2 * ks[ki]));
+    for (int pi = 0; pi < 4 && rc == LTRK_OK; ++pi) {
+      for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
+        const ltrk_plan p{ks[ki], blocks[bi], ppls[pi], 1};
+        const double ms = time_call(integrator, dtype, n, t, arrays, mom, s, ring, p, &rc);
+        if (ms > 0.0) {
+          const double rate = static_cast<double>(n) * t / ms;
+          if (rate > best_rate) {
+            best_rate = rate;
+            best = p;
+          }
         }
-      }
-    }
-  }
-  const int ks[8] = {16, 32, 64, 128, 256, 512, 1024, 2048};
-  for (int ki = 0; ki < 8 && rc == LTRK_OK; ++ki) {
-    ltrk_plan p = best;
-    p.turns_per_launch = ks[ki];
-    const int64_t t = turns < 2 * ks[ki] ? 2 * ks[ki] : turns;
-    const double ms = time_call(integrator, dtype, n, t > 4096 ? 4096 : t, arrays, mom, s, ring, p, &rc);
-    if (ms > 0.0) {
-      const double rate = static_cast<double>(n) * (t > 4096 ? 4096 : t) / ms;
-      if (rate > best_rate * 1.01) {
-        best_rate = rate;
-        best = p;
       }
     }
   }

@@ -52,6 +52,15 @@ def check_against_oracle(z, dp, mom, z0, dp0, turns, integ, ring=SPS_RING, mom_t
     zr, dr, mr = oracle.track(z0, dp0, turns, ring, integ)
     e = bucket_error(z, dp, zr, dr, ring)
     near = near_separatrix(z0, dp0, ring)
+    # plain per-coordinate relative errors, reported (undefined at zero crossings,
+    # so not bounded): p50 / p99 / max
+    for name, a, ref in (("z", z, zr), ("dp", dp, dr)):
+        nz = ref != 0.0
+        if np.any(nz):
+            rel = np.abs(np.asarray(a)[nz] - ref[nz]) / np.abs(ref[nz])
+            print("%s %s n=%d: per-coordinate relative error of %s p50 %.1e p99 %.1e max %.1e"
+                  % (label, integ, z0.size, name, np.median(rel), np.percentile(rel, 99),
+                     rel.max()))
     check_particles(e, near, turns,
                     lambda m: amplification(oracle.track, z0[m], dp0[m], turns, ring, integ),
                     label="%s %s n=%d" % (label, integ, z0.size))
