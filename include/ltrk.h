@@ -329,7 +329,7 @@ int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int int
  * at every call; default 32768, at least 16) is never captured: its launches
  * are enqueued as they are generated, in pieces of that length, with the same
  * results. The moment partials of one call take at most LTRK_SCRATCH_MB MiB
- * (read at every call; default 1024, at least 16); longer runs are finalized
+ * (read at every call; default 192, at least 16); longer runs are finalized
  * in chunks of turns, with the same results. */
 typedef struct ltrk_plan {
     int32_t turns_per_launch;

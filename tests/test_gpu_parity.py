@@ -234,16 +234,21 @@ def test_unfused_small_workload(ltrk, integ):
 def test_moments_finalized_in_chunks(ltrk):
     """A call whose moment partials exceed the scratch cap (LTRK_SCRATCH_MB)
     is finalized in chunks of whole launches: every row still matches the
-    oracle, and the particles and every moment row equal the unchunked run
+    oracle, and the particles and every moment row equal a run in one chunk
     bit for bit (each row is reduced in the same fixed order)."""
     import os
     # at 1e5 particles the default plan has 1 particle per lane: 1563 wave
     # tiles, 62.5 KB of partials per turn, so 16 MiB hold 268 rows: 19 chunks
-    # of launches of 268 turns, against one chunk of 1024-turn launches
+    # of launches of 268 turns, against one chunk of 1024-turn launches under
+    # a 1 GiB cap
     n, T = 100_000, 5000
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, 4242)
     s = torch.cuda.Stream()
-    whole = run_f64(ltrk, z0, dp0, T, "leapfrog", stream=s)
+    os.environ["LTRK_SCRATCH_MB"] = "1024"
+    try:
+        whole = run_f64(ltrk, z0, dp0, T, "leapfrog", stream=s)
+    finally:
+        del os.environ["LTRK_SCRATCH_MB"]
     os.environ["LTRK_SCRATCH_MB"] = "16"
     try:
         chunked = run_f64(ltrk, z0, dp0, T, "leapfrog", stream=s)
