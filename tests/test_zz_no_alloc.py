@@ -72,3 +72,35 @@ def test_empty_bunch_and_refusal(ltrk):
     assert err.value.code == ltrk.LTRK_EINVAL
     del big_z, big_d
     torch.cuda.empty_cache()
+
+
+def test_captured_into_a_graph(ltrk):
+    """The allocation-free call captured into a graph of the caller's own
+    (after one eager call has set the array's address up on the device):
+    every replay, with the state restored between replays, equals the eager
+    call bit for bit."""
+    z0, dp0 = gaussian_bunch(50_000, SIGMA_Z, SIGMA_DP, 62_000)
+    T = 96
+    s = torch.cuda.Stream()
+    z_init, d_init = torch.as_tensor(z0).cuda(), torch.as_tensor(dp0).cuda()
+    z, dp = z_init.clone(), d_init.clone()
+    mom = torch.empty((T, 5), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s):
+        ltrk.ltrk_track_f64_noalloc(z, dp, T, SPS_RING, "ruth4", mom, stream=s)
+    s.synchronize()
+    ref = (z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy())
+    z.copy_(z_init)
+    dp.copy_(d_init)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        ltrk.ltrk_track_f64_noalloc(z, dp, T, SPS_RING, "ruth4", mom, stream=s)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        z.copy_(z_init)
+        dp.copy_(d_init)
+        mom.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same((z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy()), ref, "replay")
