@@ -693,6 +693,7 @@ typedef struct {
     double Rs, alpha, omega_bar;
     double kappa;           /* q Q_mp / (beta p0 c): delta kick per volt of potential per count */
     double z_lo, dz;        /* slice edges z_lo + k dz */
+    double per_dz;          /* n_slices / (z_hi - z_lo): slice coordinate per metre */
     int64_t n_slices;
     double tau_per_slice;   /* dz / (beta c) */
 } or_wake;
@@ -707,10 +708,12 @@ static double wake_fn(const or_wake *w, double tau)
            (cos(w->omega_bar * tau) - w->alpha / w->omega_bar * sin(w->omega_bar * tau));
 }
 
-/* Slice of z, or -1 outside [z_lo, z_lo + n_slices dz). */
+/* Slice of z, or -1 outside the slices. The slice coordinate of z is
+ * u = (z - z_lo) * per_dz, a difference and a product each rounded once;
+ * slice k holds the u in [k, k + 1). */
 static int64_t slice_of(const or_wake *w, double z)
 {
-    double u = (z - w->z_lo) / w->dz;
+    double u = (z - w->z_lo) * w->per_dz;
     if (!(u >= 0.0))
         return -1;
     double f = floor(u);
@@ -741,7 +744,7 @@ static void wake_kick(const or_wake *w, const double *Wm, const double *z, doubl
     for (int64_t i = 0; i < n; ++i) {
         if (slice_of(w, z[i]) < 0)
             continue;
-        double s = (z[i] - w->z_lo) / w->dz - 0.5; /* in slice-centre units */
+        double s = (z[i] - w->z_lo) * w->per_dz - 0.5; /* in slice-centre units */
         double pot;
         if (s <= 0.0) {
             pot = V[0];
@@ -803,6 +806,7 @@ int oracle_track_wake(double *z, double *dp, int64_t n, int64_t turns, double C,
     w.n_slices = ns;
     w.z_lo = wk[6];
     w.dz = (wk[7] - wk[6]) / (double)ns;
+    w.per_dz = (double)ns / (wk[7] - wk[6]);
     w.tau_per_slice = w.dz / (b.beta * c_light);
     double q_mp = n > 0 ? q * e_charge * wk[4] / (double)n : 0.0;
     w.kappa = q * q_mp / (b.beta * p0c);
