@@ -32,6 +32,9 @@ hipError_t launch_wake_turn(const BunchDev& b, const CoeffsRf2& c, const WakeDev
                             int32_t row, int ppl, int block, int grid, hipStream_t s);
 // The potential w.pot from the slice counts, which it zeroes (one block).
 hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s);
+// Blocks of `block` threads of the wake turn kernel that the device holds at
+// once (all compute units; 0 if the runtime cannot tell).
+int wake_resident_blocks(int integrator, int harmonics, int ppl, int block, int n_slices);
 // Zero the slice counts (start of a call; a kernel, not a memset, so a
 // captured sequence replays correctly).
 hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s);

@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "kernels.h"
 #include "ltrk_device.h"
@@ -32,21 +33,29 @@
 
 namespace ltrk {
 
-// Slice of z, or -1 outside [z_lo, z_lo + n_slices dz).
+// Slice coordinate of z: (z - z_lo) * per_dz, a difference and a product each
+// rounded once; slice k holds the coordinates in [k, k + 1).
+__device__ __forceinline__ double slice_coord(const WakeDev& w, double z) {
+  return (z - w.z_lo) * w.per_dz;
+}
+
+// Slice of z, or -1 outside the slices (also for a non-finite z).
 __device__ __forceinline__ int slice_of(const WakeDev& w, double z) {
-  const double u = (z - w.z_lo) / w.dz;
+  const double u = slice_coord(w, z);
   if (!(u >= 0.0)) return -1;
   const double f = __builtin_floor(u);
   return f < static_cast<double>(w.n_slices) ? static_cast<int>(f) : -1;
 }
 
 // Potential at z by linear interpolation between slice centres (constant
-// beyond the first and last centre); pot is the block's LDS copy.
+// beyond the first and last centre); pot is the block's LDS copy with one more
+// entry, pot[n_slices] = pot[n_slices - 1]. Without branches: the centre
+// coordinate is clamped to [0, n_slices - 1] (a NaN to 0), and at either end
+// the weight of the neighbour is zero, so the result there is the end value
+// itself, as the unclamped definition gives.
 __device__ __forceinline__ double potential_at(const WakeDev& w, const double* pot, double z) {
-  const double s = (z - w.z_lo) / w.dz - 0.5;
-  const int last = w.n_slices - 1;
-  if (s <= 0.0) return pot[0];
-  if (s >= static_cast<double>(last)) return pot[last];
+  const double last = static_cast<double>(w.n_slices - 1);
+  const double s = __builtin_fmin(__builtin_fmax(slice_coord(w, z) - 0.5, 0.0), last);
   const double k0 = __builtin_floor(s);
   const double f = s - k0;
   const int k = static_cast<int>(k0);
@@ -69,15 +78,17 @@ template <int INTEG, int H, int P, bool KICK, bool MOM, bool STEP>
 __global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c, WakeDev w,
                                                          int32_t row) {
   extern __shared__ double lds[];
-  double* pot = lds;                                           // n_slices doubles
-  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + w.n_slices);  // n_slices counters
+  const int ns = w.n_slices;
+  double* pot = lds;                                           // ns + 1 doubles
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + ns + 1);  // ns + 1 counters, the last
+                                                               // for particles outside
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wpb = blockDim.x >> 6;
   const int64_t grid_waves = static_cast<int64_t>(gridDim.x) * wpb;
   const int64_t gw = static_cast<int64_t>(blockIdx.x) * wpb + (tid >> 6);
-  for (int k = tid; k < w.n_slices; k += blockDim.x) {
-    if constexpr (KICK) pot[k] = w.pot[k];
+  for (int k = tid; k <= ns; k += blockDim.x) {
+    if constexpr (KICK) pot[k] = w.pot[k < ns ? k : ns - 1];
     if constexpr (STEP) hist[k] = 0u;
   }
   __syncthreads();
@@ -85,45 +96,62 @@ __global__ __launch_bounds__(kMaxBlock) void k_wake_turn(BunchDev b, CoeffsRf2 c
   double* __restrict__ dpp = static_cast<double*>(b.dp);
   Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
   const Rf2Src src{c};
-  for (int64_t tile = gw; tile < b.waves; tile += grid_waves) {
+  const Centre cen = MOM ? centre_of(b.centre) : Centre{0.0, 0.0};
+  // One wave tile; FULL: every particle of the tile is in the bunch, so no
+  // lane needs a bounds check.
+  auto tile_turn = [&](int64_t tile, auto full_tile) {
+    constexpr bool FULL = decltype(full_tile)::value;
     const int64_t first = tile * static_cast<int64_t>(kWave * P) + lane;
     double z[P], d[P];
     bool live[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t i = first + static_cast<int64_t>(p) * kWave;
-      live[p] = i < b.n;
-      z[p] = live[p] ? __builtin_nontemporal_load(&zp[i]) : 0.0;
-      d[p] = live[p] ? __builtin_nontemporal_load(&dpp[i]) : 0.0;
+      live[p] = FULL || i < b.n;
+      if constexpr (FULL) {
+        z[p] = __builtin_nontemporal_load(&zp[i]);
+        d[p] = __builtin_nontemporal_load(&dpp[i]);
+      } else {
+        z[p] = live[p] ? __builtin_nontemporal_load(&zp[i]) : 0.0;
+        d[p] = live[p] ? __builtin_nontemporal_load(&dpp[i]) : 0.0;
+      }
     }
     if constexpr (KICK) {
+      // particles outside the slices keep their momentum (a select, no branch)
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        if (live[p] && slice_of(w, z[p]) >= 0) d[p] = d[p] - w.kappa * potential_at(w, pot, z[p]);
+      for (int p = 0; p < P; ++p) {
+        const double kicked = d[p] - w.kappa * potential_at(w, pot, z[p]);
+        d[p] = live[p] && slice_of(w, z[p]) >= 0 ? kicked : d[p];
+      }
     }
     if constexpr (MOM) {
       // about the call's centre (HBM-bound kernel: the subtractions cost no time)
-      const Centre cen = centre_of(b.centre);
 #pragma unroll
       for (int p = 0; p < P; ++p)
         accumulate(s, live[p] ? z[p] - cen.z : 0.0, live[p] ? d[p] - cen.d : 0.0);
     }
     if constexpr (STEP) {
-      turn_ext<INTEG, false, H, P, true>(z, d, live, c, src);
+      turn_ext<INTEG, false, H, P, !FULL>(z, d, live, c, src);
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const int k = live[p] ? slice_of(w, z[p]) : -1;
-        if (k >= 0) atomicAdd(&hist[k], 1u);
+        atomicAdd(&hist[k >= 0 ? k : ns], 1u);
       }
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t i = first + static_cast<int64_t>(p) * kWave;
-      if (live[p]) {
+      if (FULL || live[p]) {
         if constexpr (STEP) __builtin_nontemporal_store(z[p], &zp[i]);
         if constexpr (KICK || STEP) __builtin_nontemporal_store(d[p], &dpp[i]);
       }
     }
+  };
+  for (int64_t tile = gw; tile < b.waves; tile += grid_waves) {
+    if ((tile + 1) * static_cast<int64_t>(kWave * P) <= b.n)
+      tile_turn(tile, std::true_type{});
+    else
+      tile_turn(tile, std::false_type{});
   }
   if constexpr (MOM) {
     const double t[5] = {wave_sum(s.z), wave_sum(s.zz), wave_sum(s.d), wave_sum(s.dd),
@@ -247,9 +275,24 @@ hipError_t launch_wake_turn(const BunchDev& b, const CoeffsRf2& c, const WakeDev
   const bool mom = b.partials != nullptr;
   TurnFn fn = pick_turn(b.integrator, c.harmonics, phase, mom, ppl);
   if (!fn) return hipErrorInvalidValue;
-  const size_t lds = static_cast<size_t>(w.n_slices) * (sizeof(double) + sizeof(uint32_t));
+  // potential and histogram, each with one more entry (see k_wake_turn)
+  const size_t lds = static_cast<size_t>(w.n_slices + 1) * (sizeof(double) + sizeof(uint32_t));
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(grid)), dim3(block), lds, s, b, c, w, row);
   return hipGetLastError();
+}
+
+int wake_resident_blocks(int integrator, int harmonics, int ppl, int block, int n_slices) {
+  TurnFn fn = pick_turn(integrator, harmonics, 1, true, ppl);
+  if (!fn || block <= 0) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const size_t lds = static_cast<size_t>(n_slices + 1) * (sizeof(double) + sizeof(uint32_t));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                   block, lds) != hipSuccess)
+    return 0;
+  return cus * per_cu;
 }
 
 hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s) {
@@ -265,9 +308,12 @@ hipError_t launch_wake_potential(const WakeDev& w, hipStream_t s) {
 
 hipError_t launch_wake_zero(const WakeDev& w, hipStream_t s) {
   if (w.n_slices < 1 || w.n_slices > kWakeMaxSlices) return hipErrorInvalidValue;
-  // both parities' buffers (w.counts is the first of the two)
-  const int n = 2 * kWakeCountCopies * kWakeCountStride(w.n_slices);
+  // both parities' buffers
+  const int n = kWakeCountCopies * kWakeCountStride(w.n_slices);
   hipLaunchKernelGGL(k_wake_zero, dim3((n + 255) / 256), dim3(256), 0, s, w.counts, n);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wake_zero, dim3((n + 255) / 256), dim3(256), 0, s, w.clear, n);
   return hipGetLastError();
 }
 

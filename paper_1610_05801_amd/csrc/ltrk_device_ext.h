@@ -79,7 +79,8 @@ __host__ __device__ inline int lds_doubles_per_wave_6d(int turns) {
 // the wake at the lags between slice centres, the slice counts of the last
 // map step and the potential at the slice centres.
 constexpr int kWakeMaxSlices = 4096;
-constexpr int kWakeMaxBlocks = 1024;
+constexpr int kWakeMaxBlocks = 8192;
+constexpr int kWakeMinBlocks = 1024;  // blocks per round when the runtime cannot tell
 constexpr int kWakePotThreads = 256;    // block of the potential kernel
 constexpr int kWakePotSlices = 32;      // slices whose potential one block forms
 constexpr int kWakeStageSlices = 2048;  // wake table staged in LDS up to this many slices
@@ -92,6 +93,7 @@ __host__ __device__ constexpr int kWakeCountStride(int n_slices) { return (n_sli
 struct WakeDev {
   double z_lo;
   double dz;
+  double per_dz;         // n_slices / (z_hi - z_lo): slice coordinate per metre
   double kappa;          // q Q_mp / (beta p0 c): delta kick per volt of potential
   const double* wtab;    // [n_slices] W(m dz / (beta c)), W(0) half the limit
   uint32_t* counts;      // [kWakeCountCopies][stride] counts of the last map step: the
