@@ -56,6 +56,20 @@ def test_derive_matches_oracle():
         assert abs(d[a] - o[b]) <= 1e-14 * abs(o[b]), (a, d[a], o[b])
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_derive_matches_oracle_on_random_rings(seed):
+    from tests._rings import random_ring
+    ring = random_ring(seed)
+    d = ltrk.ltrk_derive(ring)
+    o = oracle.derive(ring)
+    pairs = [("gamma", "gamma"), ("beta", "beta"), ("eta", "eta"), ("kick_amplitude", "A"),
+             ("wavenumber", "k"), ("slip_length", "D"), ("omega_s", "omega"), ("q_s", "Qs"),
+             ("q_leapfrog", "Q_lf"), ("bucket_half_length", "bucket_half_length"),
+             ("bucket_height", "bucket_height"), ("h_separatrix", "H_sep")]
+    for a, b in pairs:
+        assert abs(d[a] - o[b]) <= 1e-13 * abs(o[b]), (seed, a, d[a], o[b])
+
+
 def test_derive_unstable_ring_has_nan_tune():
     d = ltrk.ltrk_derive(dict(SPS_RING, gamma_t=40.0))
     assert d["eta"] < 0 and math.isnan(d["q_s"]) and math.isnan(d["bucket_height"])
