@@ -1,10 +1,15 @@
 """Build libltrk.so (HIP for gfx950) in-tree: paper_1610_05801_amd/libltrk.so.
 
     python -m paper_1610_05801_amd.build
+    python -m paper_1610_05801_amd.build --sanitize-host OUT_DIR
 
 Every HIP source is compiled with -ffp-contract=off (the kernels spell out
 their fma() calls, so rounding is fixed by the source) and without packed
-FP32 instruction selection.
+FP32 instruction selection. --sanitize-host builds a copy into OUT_DIR whose
+host code (argument checks, plans, scratch and graph caches, the engine's
+bookkeeping) carries AddressSanitizer and UndefinedBehaviorSanitizer checks;
+device code is built as usual. Load it with LTRK_LIBRARY=OUT_DIR/libltrk.so
+in a process that preloads the ASan runtime (printed by the build).
 """
 from __future__ import annotations
 
@@ -37,9 +42,14 @@ def flags() -> list:
             "-I" + os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str) -> str:
-    out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", out]
+# host-only sanitizer flags: every -fsanitize applies to the host pass alone
+SANITIZE_HOST = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+                 "-Xarch_host -fno-omit-frame-pointer -g").split()
+
+
+def _compile(src: str, obj_dir: str = OBJ, extra: tuple = ()) -> str:
+    out = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + flags() + list(extra) + ["-c", os.path.join(CSRC, src), "-o", out]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compiling %s failed:\n%s%s" % (src, res.stdout, res.stderr))
@@ -62,6 +72,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out_dir: str) -> str:
+    """The library with host-side ASan and UBSan into out_dir; returns its path."""
+    obj = os.path.join(out_dir, "_build")
+    os.makedirs(obj, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        objs = list(pool.map(lambda s: _compile(s, obj, SANITIZE_HOST), SOURCES))
+    lib = os.path.join(out_dir, "libltrk.so")
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-shared-libasan"] + \
+        SANITIZE_HOST[:4] + ["-o", lib] + objs
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("linking the sanitized libltrk.so failed:\n%s%s" %
+                           (res.stdout, res.stderr))
+    rt = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                        capture_output=True, text=True).stdout.strip()
+    print("built %s\nASan runtime to preload: %s" % (lib, rt))
+    return lib
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) == 3 and sys.argv[1] == "--sanitize-host":
+        build_sanitized(os.path.abspath(sys.argv[2]))
+    else:
+        build(verbose=True)
     sys.exit(0)
