@@ -134,16 +134,26 @@ def _oracle_rate(z0, dp0, turns_total, ring, threads, budget_s):
 
 
 def host_cpu_model() -> str:
-    """The CPU model name from /proc/cpuinfo (the machine type where there is none)."""
+    """The CPU model name from /proc/cpuinfo with its family, model and
+    stepping numbers (a virtual machine may report only a generic name); the
+    machine type where there is none."""
     import platform
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # the first processor's block
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
     except OSError:
         pass
-    return platform.processor() or platform.machine()
+    name = fields.get("model name")
+    if not name:
+        return platform.processor() or platform.machine()
+    ids = ", ".join("%s %s" % (k.replace("cpu ", ""), fields[k])
+                    for k in ("cpu family", "model", "stepping") if k in fields)
+    return "%s (%s)" % (name, ids) if ids else name
 
 
 def cpu_baseline(n, turns_total, ring, seed, budget_s=10.0):
