@@ -279,7 +279,9 @@ typedef struct ltrk_wake {
 
 /* The extended map (as ltrk_track_rf2_f64) with a wake kick after every
  * step: the bunch is cut into n_slices equal slices over [z_lo, z_hi)
- * (particles outside are neither counted nor kicked), the potential at slice
+ * (particles outside are neither counted nor kicked; the slice coordinate of
+ * z is u = (z - z_lo) * (n_slices / (z_hi - z_lo)), each operation rounded
+ * once, and slice k holds u in [k, k + 1)), the potential at slice
  * centre k is V_k = Q_mp sum_{j >= k} count_j W((j - k) dz / (beta c)) with
  * Q_mp = q e intensity / n, and a particle at z gets
  *   delta <- delta - q V(z) / (beta p0 c),
