@@ -153,7 +153,7 @@ int ltrk_track_f64(double* z, double* dp, int64_t n, int64_t turns, const ltrk_r
  * in chunks of turns whose partials fit the array. EINVAL, before anything is
  * enqueued, for arguments ltrk_track_f64 rejects and when moments are
  * requested for a bunch whose partials of one turn exceed the array (beyond
- * about 8.5e8 particles at 8 per lane). All calls on one device share its array: calls that
+ * about 8.5e8 particles at 8 per lane, 1.7e9 at 16). All calls on one device share its array: calls that
  * overlap on that device (other streams or threads) race and give wrong
  * moments; the array's contents between calls are unspecified (every row a
  * call reads is written by that call first). */
@@ -325,7 +325,10 @@ int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int int
 
 /* Launch plan. turns_per_launch K: turns fused per kernel launch (1 = one
  * launch per turn, the unfused form); block: threads per block (64, 128 or
- * 256); ppl: particles per lane (1, 2, 4 or 8); use_graph: replay the launch
+ * 256); ppl: particles per lane (1, 2, 4, 8 or 16; 16 is used by single-bunch
+ * FP64 calls only: FP32 + Kahan, batched and wake calls take at most 8,
+ * extended-map and wake calls at least 4, with the same results as at that
+ * value); use_graph: replay the launch
  * sequence from a cached hipGraph (streams other than NULL only). A call of
  * more launches than the environment variable LTRK_MAX_GRAPH_LAUNCHES (read
  * at every call; default 32768, at least 16) is never captured: its launches
@@ -343,10 +346,12 @@ typedef struct ltrk_plan {
 /* Force one plan for all following calls of this process (NULL: back to
  * automatic plans from the tuning cache or the built-in default). EINVAL for
  * values outside the ranges above. Forced and tuned plans are used as given;
- * the built-in default (1024 turns per launch) is lowered, for calls that
- * compute moments, to the largest power of two (at least 64) whose moment
- * partials of one launch stay within 192 MiB, e.g. 256 turns at 1e7
- * particles. */
+ * the built-in default (1024 turns per launch; 8 particles per lane from
+ * ~1e5 particles, 16 for single-bunch FP64 calls where the waves then fill
+ * the device's wave slots in fewer rounds, e.g. from 6e6 particles) is
+ * lowered, for calls that compute moments, to the largest power of two (at
+ * least 64) whose moment partials of one launch stay within 192 MiB, e.g.
+ * 512 turns at 1e7 particles (16 per lane). */
 int ltrk_set_plan(const ltrk_plan* plan);
 
 /* The plan a call with these parameters would use now. */
@@ -355,7 +360,8 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
 /* Time candidate plans on scratch particles of size n (on `stream`,
  * synchronising it): every combination of 32, 128, 256, 512, 1024 and 2048
  * turns per launch, 64, 128 and 256 threads per block and 1, 2, 4 and 8
- * particles per lane, with moments. Cache the fastest for single-bunch calls
+ * particles per lane (and 16 for LTRK_F64), with moments. Cache the fastest
+ * for single-bunch calls
  * of (device, integrator, dtype, floor(log2 n)). `best` (host, may be NULL)
  * receives it. */
 int ltrk_autotune(int integrator, int dtype, int64_t n, void* stream, ltrk_plan* best);

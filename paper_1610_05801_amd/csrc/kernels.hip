@@ -562,20 +562,31 @@ using SingleFn = void (*)(BunchDev, int32_t);
 using TilesFn = void (*)(const BunchDev*, const TileDev*, int32_t, int32_t);
 using MixedFn = void (*)(const BunchDev*, const TileDev*);
 
+// 16 particles per lane only for the FP64 state: its kernels take ~230 VGPRs
+// and keep two waves per SIMD; the FP32 + Kahan kernels would take up to 268.
 template <int I, int D>
-constexpr SingleFn single_fn(int pi) {
-  return pi == 0 ? k_track_single<I, D, 1>
-       : pi == 1 ? k_track_single<I, D, 2>
-       : pi == 2 ? k_track_single<I, D, 4>
-                 : k_track_single<I, D, 8>;
+SingleFn single_fn(int pi) {
+  switch (pi) {
+    case 0: return k_track_single<I, D, 1>;
+    case 1: return k_track_single<I, D, 2>;
+    case 2: return k_track_single<I, D, 4>;
+    case 3: return k_track_single<I, D, 8>;
+    case 4:
+      if constexpr (D == kF64) return k_track_single<I, D, 16>;
+      return nullptr;
+    default: return nullptr;
+  }
 }
 
 template <int I, int D>
-constexpr TilesFn tiles_fn(int pi) {
-  return pi == 0 ? k_track_tiles<I, D, 1>
-       : pi == 1 ? k_track_tiles<I, D, 2>
-       : pi == 2 ? k_track_tiles<I, D, 4>
-                 : k_track_tiles<I, D, 8>;
+TilesFn tiles_fn(int pi) {
+  switch (pi) {
+    case 0: return k_track_tiles<I, D, 1>;
+    case 1: return k_track_tiles<I, D, 2>;
+    case 2: return k_track_tiles<I, D, 4>;
+    case 3: return k_track_tiles<I, D, 8>;
+    default: return nullptr;
+  }
 }
 
 SingleFn pick_single(int integ, int dtype, int pi) {
@@ -606,7 +617,8 @@ MixedFn pick_mixed(int pi) {
     case 0: return k_track_mixed<1>;
     case 1: return k_track_mixed<2>;
     case 2: return k_track_mixed<4>;
-    default: return k_track_mixed<8>;
+    case 3: return k_track_mixed<8>;
+    default: return nullptr;
   }
 }
 
@@ -645,9 +657,11 @@ hipError_t launch_track_mixed(const BunchDev* bunches, const TileDev* tiles, int
                               int ppl, int block, hipStream_t s) {
   const int pi = ppl_index(ppl);
   if (pi < 0 || block % kWave != 0 || block > kMaxBlock || block <= 0) return hipErrorInvalidValue;
+  const MixedFn fn = pick_mixed(pi);
+  if (!fn) return hipErrorInvalidValue;
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pick_mixed(pi), dim3(static_cast<unsigned>(ntiles)), dim3(block),
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(ntiles)), dim3(block),
                      lds_bytes(block, true, kFlushTurns), s, bunches, tiles);
   return hipGetLastError();
 }

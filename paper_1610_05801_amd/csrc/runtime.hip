@@ -978,7 +978,10 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   if ((rc = current_device(&dev))) return rc;
   bool default_plan = false;
   ltrk_plan plan = choose_plan(integrator, dtype, n, false, &default_plan);
-  if (ext) plan.ppl = std::max(plan.ppl, 4);  // extended kernels: 4 or 8 particles per lane
+  // extended kernels: 4 or 8 particles per lane; 16 is compiled for the plain
+  // FP64 kernels only
+  if (ext) plan.ppl = std::min(std::max(plan.ppl, 4), 8);
+  if (dtype != LTRK_F64) plan.ppl = std::min(plan.ppl, 8);
   if (mom && default_plan)
     plan.turns_per_launch = static_cast<int32_t>(default_turns_for_partials(
         plan.turns_per_launch,
@@ -1371,7 +1374,7 @@ static int track_wake(double* z, double* dp, int64_t n, int64_t turns, const ltr
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
   ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false);
-  const int ppl = std::max(plan.ppl, 4);
+  const int ppl = std::min(std::max(plan.ppl, 4), 8);  // the wake kernels: 4 or 8
   const int block = plan.block;
   const int wpb = block / kWave;
 
@@ -1613,7 +1616,8 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   if (total_n == 0) return LTRK_OK;
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  const ltrk_plan plan = choose_plan(integrator, dtype, total_n, true);
+  ltrk_plan plan = choose_plan(integrator, dtype, total_n, true);
+  plan.ppl = std::min(plan.ppl, 8);  // the tile kernels are compiled for 1 to 8
   const int wpb = plan.block / kWave;
 
   std::vector<BunchDev> bd(nb);

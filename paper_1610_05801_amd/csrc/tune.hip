@@ -42,7 +42,7 @@ std::map<TuneKey, ltrk_plan> g_tuned;
 bool plan_valid(const ltrk_plan& p) {
   const bool k_ok = p.turns_per_launch >= 1 && p.turns_per_launch <= 65536;
   const bool b_ok = p.block == 64 || p.block == 128 || p.block == 256;
-  const bool p_ok = p.ppl == 1 || p.ppl == 2 || p.ppl == 4 || p.ppl == 8;
+  const bool p_ok = p.ppl == 1 || p.ppl == 2 || p.ppl == 4 || p.ppl == 8 || p.ppl == 16;
   return k_ok && b_ok && p_ok && (p.use_graph == 0 || p.use_graph == 1);
 }
 
@@ -82,7 +82,12 @@ int log2_bucket(int64_t n) {
 
 }  // namespace
 
-ltrk_plan default_plan(int /*integrator*/, int /*dtype*/, int64_t n, bool /*batched*/) {
+// Wave slots of the single-bunch kernels on the device (256 CUs x 4 SIMDs x
+// 2 waves) and the relative cost of a particle at 16 per lane against 8.
+constexpr int64_t kWaveSlots = 2048;
+constexpr double kCostPerSlot16 = 0.93;
+
+ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool batched) {
   ltrk_plan p;
   // 1024 turns per launch: 1.2-1.6% over 512 at 1e6 particles (fewer launch
   // boundaries), while a launch's moment partials (80 MB at 1e6 particles)
@@ -102,6 +107,22 @@ ltrk_plan default_plan(int /*integrator*/, int /*dtype*/, int64_t n, bool /*batc
     p.ppl = 2;
   else
     p.ppl = 1;
+  // 16 particles per lane (single-bunch FP64 only) halve the per-particle
+  // share of the moment reduction and of the partials, and still run two
+  // waves per SIMD; a lane's particles cost ~7% less than at 8 (measured
+  // 1.57e12 against 1.49e12 at 1e7 particles, 1.59e12 against 1.46e12 at
+  // 4e7). The kernels hold two waves per SIMD (the LDS rows, and ~230 VGPRs
+  // at 16), so waves run in rounds of kWaveSlots and a launch lasts
+  // ceil(waves / kWaveSlots) rounds of P particles each: 16 is taken where
+  // that costs less (2e6, 4e6 and from 6e6 particles on; not at 1e6, where it
+  // would leave one wave per SIMD: 1.25e12 against 1.43e12, nor at 3e6 or
+  // 5e6, where the last round would be a small one).
+  if (dtype == LTRK_F64 && !batched && p.ppl == 8) {
+    auto rounds = [&](int ppl) { return (waves_for(n, ppl) + kWaveSlots - 1) / kWaveSlots; };
+    if (static_cast<double>(rounds(16)) * 16.0 * kCostPerSlot16 <
+        static_cast<double>(rounds(8)) * 8.0)
+      p.ppl = 16;
+  }
   if (waves_for(n, p.ppl) < 1024) p.block = 64;
   return p;
 }
@@ -213,12 +234,13 @@ int autotune(int integrator, int dtype, int64_t n, hipStream_t s, ltrk_plan* bes
   // probe call runs at least two launches of its plan.
   ltrk_plan best{128, 256, 4, 1};
   double best_rate = -1.0;
-  const int ppls[4] = {1, 2, 4, 8};
+  const int ppls[5] = {1, 2, 4, 8, 16};
+  const int n_ppls = dtype == LTRK_F64 ? 5 : 4;  // 16: FP64 kernels only
   const int blocks[3] = {64, 128, 256};
   const int ks[6] = {32, 128, 256, 512, 1024, 2048};
   for (int ki = 0; ki < 6 && rc == LTRK_OK; ++ki) {
     const int64_t t = std::min<int64_t>(4096, std::max<int64_t>(turns, 2 * ks[ki]));
-    for (int pi = 0; pi < 4 && rc == LTRK_OK; ++pi) {
+    for (int pi = 0; pi < n_ppls && rc == LTRK_OK; ++pi) {
       for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
         const ltrk_plan p{ks[ki], blocks[bi], ppls[pi], 1};
         const double ms = time_call(integrator, dtype, n, t, arrays, mom, s, ring, p, &rc);

@@ -357,13 +357,15 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, const Exact& exact, 
 // ---------------------------------------------------------------------------
 // Launch-shape helpers (host)
 
-// Index of a particles-per-lane value among the compiled ones (1, 2, 4, 8).
+// Index of a particles-per-lane value among the compiled ones (1, 2, 4, 8;
+// 16 for the single-bunch FP64 kernels only).
 inline int ppl_index(int ppl) {
   switch (ppl) {
     case 1: return 0;
     case 2: return 1;
     case 4: return 2;
     case 8: return 3;
+    case 16: return 4;
     default: return -1;
   }
 }

@@ -80,7 +80,7 @@ def test_small_workload_all_schemes(ltrk, integ):
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 257, 4097, 100_003])
-@pytest.mark.parametrize("ppl", [1, 2, 4, 8])
+@pytest.mark.parametrize("ppl", [1, 2, 4, 8, 16])
 def test_sizes_and_tiles(ltrk, n, ppl):
     """Ragged tails and several tiles for every particles-per-lane value."""
     z0, dp0 = gaussian_bunch(n, SIGMA_Z, SIGMA_DP, 7000 + n)
@@ -131,6 +131,53 @@ def test_invariance_across_k_block_graph_and_split(ltrk):
     assert np.array_equal(z.cpu().numpy(), ref[0])
     assert np.array_equal(dp.cpu().numpy(), ref[1])
     assert np.array_equal(np.vstack([m1.cpu().numpy(), m2.cpu().numpy()]), ref[2])
+
+
+@pytest.mark.parametrize("integ", INTEGS)
+def test_sixteen_per_lane_invariance_and_clamps(ltrk, integ):
+    """16 particles per lane (single-bunch FP64): bit-identical across turns
+    per launch, block and graph replay, and against the oracle; F32C calls and
+    the extended map under a forced 16 run with 8 (bit-identical to a forced
+    8), as the header states."""
+    z0, dp0 = gaussian_bunch(70_001, SIGMA_Z, SIGMA_DP, 16)
+    ref = None
+    try:
+        for K, block, graph in [(1, 256, 0), (37, 64, 1), (200, 128, 0), (300, 256, 1)]:
+            ltrk.ltrk_set_plan(K, block, 16, graph)
+            out = run_f64(ltrk, z0, dp0, 300, integ)
+            if ref is None:
+                ref = out
+                check_against_oracle(*out, z0, dp0, 300, integ, label="P=16")
+            else:
+                for a, b in zip(out, ref):
+                    assert np.array_equal(a, b), (K, block, graph)
+        rf = dict(SPS_RING, phi1_rad=0.0, harmonic2=0.0, voltage2_V=0.0, phi2_rad=0.0,
+                  eta1=0.0, eta2=0.0)
+        outs = []
+        for ppl in (16, 8):
+            ltrk.ltrk_set_plan(64, 256, ppl, 0)
+            z, dp = dev(z0), dev(dp0)
+            mom = torch.empty((50, 5), dtype=torch.float64, device="cuda")
+            ltrk.ltrk_track_rf2_f64(z, dp, 50, rf, integ, mom)
+            torch.cuda.synchronize()
+            outs.append((z.cpu().numpy(), dp.cpu().numpy(), mom.cpu().numpy()))
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+        from synth import split_f32c
+        zh, zc = split_f32c(z0)
+        dh, dc = split_f32c(dp0)
+        outs = []
+        for ppl in (16, 8):
+            ltrk.ltrk_set_plan(64, 256, ppl, 0)
+            t = [torch.as_tensor(a).cuda() for a in (zh, dh, zc, dc)]
+            mom = torch.empty((50, 5), dtype=torch.float64, device="cuda")
+            ltrk.ltrk_track_f32c(t[0], t[1], t[2], t[3], 50, SPS_RING, integ, mom)
+            torch.cuda.synchronize()
+            outs.append([a.cpu().numpy() for a in t] + [mom.cpu().numpy()])
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+    finally:
+        ltrk.ltrk_set_plan()
 
 
 def test_moments_only_entry_point(ltrk):

@@ -38,8 +38,9 @@ def test_timing_counts_launches(ltrk):
 def test_default_plan_follows_the_moment_partials(ltrk):
     """The default plan's 1024 turns per launch are lowered for calls with
     moments so that one launch's partial rows stay within 192 MiB: at 1e7
-    particles (8 per lane, 19532 wave tiles, 781 KB per row) 256 turns; at
-    1e6 (78 KB per row) the full 1024; without moments nothing changes."""
+    particles (16 per lane, 9766 wave tiles, 391 KB per row) 512 turns; at
+    1e6 (8 per lane, 78 KB per row) the full 1024; without moments nothing
+    changes."""
     ltrk.ltrk_set_plan()
 
     def launches(n, turns, moments):
@@ -53,8 +54,11 @@ def test_default_plan_follows_the_moment_partials(ltrk):
         ltrk.ltrk_timing_enable(False)
         return t["track_launches"]
 
-    assert ltrk.ltrk_get_plan("leapfrog", "f64", 10_000_000)["turns_per_launch"] == 1024
-    assert launches(10_000_000, 1024, True) == 4
+    plan = ltrk.ltrk_get_plan("leapfrog", "f64", 10_000_000)
+    assert plan["turns_per_launch"] == 1024 and plan["ppl"] == 16
+    assert ltrk.ltrk_get_plan("leapfrog", "f64", 1_000_000)["ppl"] == 8
+    assert ltrk.ltrk_get_plan("leapfrog", "f32c", 10_000_000)["ppl"] == 8
+    assert launches(10_000_000, 1024, True) == 2
     assert launches(10_000_000, 1024, False) == 1
     assert launches(1_000_000, 2048, True) == 2
 
@@ -238,7 +242,7 @@ def test_capture_refusals_enqueue_nothing(ltrk):
 def test_autotune_and_cache_roundtrip(ltrk, tmp_path):
     n = 200_000
     best = ltrk.ltrk_autotune("leapfrog", "f64", n)
-    assert best["ppl"] in (1, 2, 4, 8) and best["block"] in (64, 128, 256)
+    assert best["ppl"] in (1, 2, 4, 8, 16) and best["block"] in (64, 128, 256)
     assert 16 <= best["turns_per_launch"] <= 2048
     assert ltrk.ltrk_get_plan("leapfrog", "f64", n) == best
     path = str(tmp_path / "tune.txt")

@@ -62,13 +62,18 @@ def test_empty_bunch_and_refusal(ltrk):
     ltrk.ltrk_track_f64_noalloc(z, z, 4, SPS_RING, "leapfrog", mom)
     torch.cuda.synchronize()
     assert torch.isnan(mom).all()
-    # one turn of partials for 9e8 particles (8 per lane) exceeds the array
+    # one turn of partials for 9e8 particles at 8 per lane (70 MB) exceeds the
+    # array (the default plan would take 16 per lane there: 35 MB)
     n = 900_000_000
     big_z = torch.zeros(n, dtype=torch.float64, device="cuda")
     big_d = torch.zeros(n, dtype=torch.float64, device="cuda")
     mom1 = torch.empty((1, 5), dtype=torch.float64, device="cuda")
-    with pytest.raises(ltrk.LtrkError) as err:
-        ltrk.ltrk_track_f64_noalloc(big_z, big_d, 1, SPS_RING, "leapfrog", mom1)
+    ltrk.ltrk_set_plan(1024, 256, 8, 1)
+    try:
+        with pytest.raises(ltrk.LtrkError) as err:
+            ltrk.ltrk_track_f64_noalloc(big_z, big_d, 1, SPS_RING, "leapfrog", mom1)
+    finally:
+        ltrk.ltrk_set_plan()
     assert err.value.code == ltrk.LTRK_EINVAL
     del big_z, big_d
     torch.cuda.empty_cache()
