@@ -325,10 +325,10 @@ int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int int
 
 /* Launch plan. turns_per_launch K: turns fused per kernel launch (1 = one
  * launch per turn, the unfused form); block: threads per block (64, 128 or
- * 256); ppl: particles per lane (1, 2, 4, 8 or 16; 16 is used by single-bunch
- * FP64 calls only: FP32 + Kahan, batched and wake calls take at most 8,
- * extended-map and wake calls at least 4, with the same results as at that
- * value); use_graph: replay the launch
+ * 256); ppl: particles per lane (1, 2, 4, 8 or 16; 16 is used by FP64
+ * single-bunch and batched calls only: FP32 + Kahan, extended-map and wake
+ * calls take at most 8, extended-map and wake calls at least 4, with the same
+ * results as at that value); use_graph: replay the launch
  * sequence from a cached hipGraph (streams other than NULL only). A call of
  * more launches than the environment variable LTRK_MAX_GRAPH_LAUNCHES (read
  * at every call; default 32768, at least 16) is never captured: its launches
@@ -347,8 +347,8 @@ typedef struct ltrk_plan {
  * automatic plans from the tuning cache or the built-in default). EINVAL for
  * values outside the ranges above. Forced and tuned plans are used as given;
  * the built-in default (1024 turns per launch; 8 particles per lane from
- * ~1e5 particles, 16 for single-bunch FP64 calls where the waves then fill
- * the device's wave slots in fewer rounds, e.g. from 6e6 particles) is
+ * ~1e5 particles, 16 for FP64 calls where the waves then fill the device's
+ * wave slots in fewer rounds, e.g. from 6e6 particles in all) is
  * lowered, for calls that compute moments, to the largest power of two (at
  * least 64) whose moment partials of one launch stay within 192 MiB, e.g.
  * 512 turns at 1e7 particles (16 per lane). */
@@ -375,7 +375,8 @@ int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan*
  * its arrays are not touched): probe bunches of those sizes and rings are
  * tracked on `stream` (synchronised) with every combination of 128, 256, 512
  * and 1024 turns per launch, 64, 128 and 256 threads per block and 2, 4 and 8
- * particles per lane, and the fastest plan is cached for batched calls of
+ * particles per lane (and 16 for LTRK_F64), and the fastest plan is cached for
+ * batched calls of
  * (device, integrator, dtype, floor(log2 of the total particles)). Needs
  * device memory for the probes' state and 4096 moment rows per bunch with
  * moments. `best` (host, may be NULL) receives the plan. */

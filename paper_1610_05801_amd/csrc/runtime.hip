@@ -1617,7 +1617,8 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
   ltrk_plan plan = choose_plan(integrator, dtype, total_n, true);
-  plan.ppl = std::min(plan.ppl, 8);  // the tile kernels are compiled for 1 to 8
+  // 16 particles per lane: FP64 tile kernels only
+  if (dtype != LTRK_F64) plan.ppl = std::min(plan.ppl, 8);
   const int wpb = plan.block / kWave;
 
   std::vector<BunchDev> bd(nb);

@@ -87,7 +87,7 @@ int log2_bucket(int64_t n) {
 constexpr int64_t kWaveSlots = 2048;
 constexpr double kCostPerSlot16 = 0.93;
 
-ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool batched) {
+ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool /*batched*/) {
   ltrk_plan p;
   // 1024 turns per launch: 1.2-1.6% over 512 at 1e6 particles (fewer launch
   // boundaries), while a launch's moment partials (80 MB at 1e6 particles)
@@ -107,7 +107,8 @@ ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool batched) {
     p.ppl = 2;
   else
     p.ppl = 1;
-  // 16 particles per lane (single-bunch FP64 only) halve the per-particle
+  // 16 particles per lane (FP64 only; a batched call counts the waves of
+  // all its bunches) halve the per-particle
   // share of the moment reduction and of the partials, and still run two
   // waves per SIMD; a lane's particles cost ~7% less than at 8 (measured
   // 1.57e12 against 1.49e12 at 1e7 particles, 1.59e12 against 1.46e12 at
@@ -117,7 +118,7 @@ ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool batched) {
   // that costs less (2e6, 4e6 and from 6e6 particles on; not at 1e6, where it
   // would leave one wave per SIMD: 1.25e12 against 1.43e12, nor at 3e6 or
   // 5e6, where the last round would be a small one).
-  if (dtype == LTRK_F64 && !batched && p.ppl == 8) {
+  if (dtype == LTRK_F64 && p.ppl == 8) {
     auto rounds = [&](int ppl) { return (waves_for(n, ppl) + kWaveSlots - 1) / kWaveSlots; };
     if (static_cast<double>(rounds(16)) * 16.0 * kCostPerSlot16 <
         static_cast<double>(rounds(8)) * 8.0)
@@ -378,12 +379,13 @@ int autotune_batched(const ltrk_bunch* bunches, int nb, int integrator, int dtyp
   }
   ltrk_plan best{256, 256, 8, 1};
   double best_rate = -1.0;
-  const int ppls[3] = {2, 4, 8};
+  const int ppls[4] = {2, 4, 8, 16};
+  const int n_ppls = dtype == LTRK_F64 ? 4 : 3;  // 16: FP64 tile kernels only
   const int blocks[3] = {64, 128, 256};
   const int ks[4] = {128, 256, 512, 1024};
   for (int ki = 0; ki < 4 && rc == LTRK_OK; ++ki) {
     const int64_t turns = std::min<int64_t>(4096, std::max<int64_t>(base_turns, 2 * ks[ki]));
-    for (int pi = 0; pi < 3 && rc == LTRK_OK; ++pi) {
+    for (int pi = 0; pi < n_ppls && rc == LTRK_OK; ++pi) {
       for (int bi = 0; bi < 3 && rc == LTRK_OK; ++bi) {
         const ltrk_plan p{ks[ki], blocks[bi], ppls[pi], 1};
         const double ms = time_batched(table, turns, integrator, dtype, s, p, &rc);

@@ -38,10 +38,11 @@ def make(spec):
     return gaussian_bunch(spec.n, matched_sigma_z(r, spec.sigma_dp), spec.sigma_dp, spec.seed)
 
 
+@pytest.mark.parametrize("ppl", [4, 16])
 @pytest.mark.parametrize("integ", ["leapfrog", "ruth4"])
-def test_batched_f64_matches_oracle_and_alone(ltrk, integ):
+def test_batched_f64_matches_oracle_and_alone(ltrk, integ, ppl):
     T = 300
-    ltrk.ltrk_set_plan(64, 256, 4, 1)
+    ltrk.ltrk_set_plan(64, 256, ppl, 1)
     stream = torch.cuda.Stream()
     bunches, inits = [], []
     for s in SPECS:
@@ -121,7 +122,7 @@ def test_autotuned_batched_plan_matches_oracle(ltrk):
     stream = torch.cuda.Stream()
     tuned = ltrk.ltrk_autotune_batched(bunches, "ruth4", "f64", stream=stream)
     assert tuned["turns_per_launch"] in (128, 256, 512, 1024)
-    assert tuned["block"] in (64, 128, 256) and tuned["ppl"] in (2, 4, 8)
+    assert tuned["block"] in (64, 128, 256) and tuned["ppl"] in (2, 4, 8, 16)
     assert ltrk.ltrk_get_plan_batched("ruth4", "f64", total) == tuned
     # the probe bunches left the caller's arrays alone
     assert np.array_equal(bunches[0]["z"].cpu().numpy(), inits[0][0])
