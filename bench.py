@@ -92,11 +92,17 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the benchmark kernel is built from, with comments
+    and blank space removed (a comment edit does not change the kernel)."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1610_05801_amd", "csrc")
     for f in ("kernels.hip", "wave.h", "ltrk_device.h", "sinpi_coeffs.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
