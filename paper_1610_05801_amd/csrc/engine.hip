@@ -24,7 +24,11 @@
 namespace ltrk {
 namespace {
 
-constexpr int kEnginePpl = 8;   // as the single-bunch default for large bunches
+// 8 particles per lane: one mixed launch runs FP64 and FP32 + Kahan tiles of
+// every scheme, and at 16 its FP32 + Kahan branches would take up to 268
+// VGPRs (one wave per SIMD); single-bunch and batched FP64 calls use 16
+// where it pays.
+constexpr int kEnginePpl = 8;
 constexpr int kEngineBlock = 256;
 constexpr int kDepth = 2;  // steps in flight
 
