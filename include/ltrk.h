@@ -354,7 +354,9 @@ typedef struct ltrk_plan {
  * 512 turns at 1e7 particles (16 per lane). */
 int ltrk_set_plan(const ltrk_plan* plan);
 
-/* The plan a call with these parameters would use now. */
+/* The plan a call with these parameters would use now (particles per lane
+ * as the call takes them for this dtype; turns per launch before the limit
+ * for calls that compute moments). */
 int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
 
 /* Time candidate plans on scratch particles of size n (on `stream`,

@@ -443,6 +443,7 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out) {
   if (!valid_integrator(integrator) || !valid_dtype(dtype) || n < 0)
     return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
   *out = choose_plan(integrator, dtype, n, false);
+  if (dtype != LTRK_F64) out->ppl = std::min(out->ppl, 8);  // as the call does
   return LTRK_OK;
 }
 
@@ -452,6 +453,7 @@ int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan*
   if (!valid_integrator(integrator) || !valid_dtype(dtype) || total_n < 0)
     return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
   *out = choose_plan(integrator, dtype, total_n, true);
+  if (dtype != LTRK_F64) out->ppl = std::min(out->ppl, 8);  // as the call does
   return LTRK_OK;
 }
 
