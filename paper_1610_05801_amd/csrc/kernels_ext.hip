@@ -312,8 +312,8 @@ ProgFn prog_fn(int ppl) {
 }
 
 template <int I, int H>
-SixdFn sixd_fn(int) {
-  return k_track_6d<I, 4, H>;
+SixdFn sixd_fn(int ppl) {
+  return ppl == 8 ? k_track_6d<I, 8, H> : k_track_6d<I, 4, H>;
 }
 
 bool valid_block(int block) { return block > 0 && block <= kMaxBlock && block % kWave == 0; }
@@ -390,7 +390,7 @@ hipError_t launch_track_prog(const BunchDev& b, const CoeffsRf2& c, const double
 
 hipError_t launch_track_6d(const Bunch6Dev& b, const Coeffs6d& c, int32_t row0, int ppl,
                            int block, hipStream_t s) {
-  if (ppl != 4 || !valid_block(block)) return hipErrorInvalidValue;
+  if ((ppl != 4 && ppl != 8) || !valid_block(block)) return hipErrorInvalidValue;
   SixdFn fn = by_scheme<PickSixd, SixdFn>(b.integrator, c.rf.harmonics, ppl);
   if (!fn) return hipErrorInvalidValue;
   const int64_t blocks = blocks_for(b.waves, block);

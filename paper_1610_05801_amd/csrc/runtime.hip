@@ -1255,11 +1255,18 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   if ((rc = current_device(&dev))) return rc;
   bool default_plan = false;
   ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false, &default_plan);
-  // six FP64 coordinates per particle: 4 particles per lane
-  constexpr int ppl = 4;
+  // six FP64 coordinates per particle: 4 or 8 particles per lane (8 takes
+  // ~177 VGPRs and still two waves per SIMD; at 1e6 particles, same box, it
+  // ran leap-frog 2.42e11 against 2.24e11 with 4 and Ruth4 1.64e11 against
+  // 1.51e11, both at 256 turns per launch). The default plan takes at most
+  // 256 turns per launch here (with 8 per lane: leap-frog 2.43e11 at 512,
+  // Ruth4 1.58e11 at 512 against 1.64e11 at 256).
+  const int ppl = std::min(std::max(plan.ppl, 4), 8);
   if (mom && default_plan)
-    plan.turns_per_launch = static_cast<int32_t>(default_turns_for_partials(
-        plan.turns_per_launch, 15 * waves_for(n, ppl) * static_cast<int64_t>(sizeof(double))));
+    plan.turns_per_launch = static_cast<int32_t>(std::min<int64_t>(
+        256, default_turns_for_partials(
+                 plan.turns_per_launch,
+                 15 * waves_for(n, ppl) * static_cast<int64_t>(sizeof(double)))));
 
   Bunch6Dev b;
   std::memset(&b, 0, sizeof(b));
@@ -1320,7 +1327,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
       bl.partials = static_cast<double*>(scratch);
       const int32_t row0 = static_cast<int32_t>(j);
       const int block = plan.block;
-      seq.push({kTimeTrack, [bl, c6, row0, block](hipStream_t st) {
+      seq.push({kTimeTrack, [bl, c6, row0, ppl, block](hipStream_t st) {
                        return launch_track_6d(bl, c6, row0, ppl, block, st);
                      }});
     }
