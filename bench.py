@@ -97,7 +97,7 @@ def kernel_source_hash() -> str:
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1610_05801_amd", "csrc")
-    for f in ("kernels.hip", "wave.h", "ltrk_device.h", "sinpi_coeffs.h"):
+    for f in ("kernels.hip", "wave.h", "ltrk_device.h", "sinpi_coeffs.h", "sinpi32_coeffs.h"):
         with open(os.path.join(csrc, f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
@@ -1360,6 +1360,46 @@ def summarize_valu(csv_path, out_path, turns_per_launch):
     print("\n".join(out))
 
 
+def summarize_valu_f32c(valu_csv, out_path, turns_per_launch):
+    """Condense a rocprofv3 --pmc CSV of --workload counters_f32c (SQ_INSTS_VALU
+    and its FP32 / FP64 FMA, ADD, MUL parts, GRBM_GUI_ACTIVE) into a per-launch
+    markdown table: instructions per particle-turn, executed FP32 and FP64
+    TFLOP/s, clock and issue utilisation at 4 cycles per wave instruction."""
+    import csv
+    rows = {}
+    with open(valu_csv) as f:
+        for r in csv.DictReader(f):
+            if "k_track_single" not in r["Kernel_Name"]:
+                continue
+            d = rows.setdefault(int(r["Dispatch_Id"]), {
+                "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+    pt = 1_000_000 * turns_per_launch
+    out = ["| Launch | Duration [us] | VALU instr / pt | FP32 FMA / ADD / MUL per pt | "
+           "FP64 FMA / ADD / MUL per pt | FP32 TFLOP/s | FP64 TFLOP/s | clock [GHz] | "
+           "VALU issue util |", "|---|---|---|---|---|---|---|---|---|"]
+    for i, (_, d) in enumerate(sorted(rows.items())):
+        per = {k: d.get(k, 0.0) * 64 / pt for k in (
+            "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+            "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+            "SQ_INSTS_VALU_MUL_F64")}
+        secs = d["ns"] * 1e-9
+        cycles = d.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        f32 = 2 * per["SQ_INSTS_VALU_FMA_F32"] + per["SQ_INSTS_VALU_ADD_F32"] + per["SQ_INSTS_VALU_MUL_F32"]
+        f64 = 2 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_ADD_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
+        out.append("| %d | %.1f | %.2f | %.2f / %.2f / %.2f | %.2f / %.2f / %.2f | %.2f | %.2f | "
+                   "%.2f | %.2f |" % (
+                       i, d["ns"] / 1e3, per["SQ_INSTS_VALU"], per["SQ_INSTS_VALU_FMA_F32"],
+                       per["SQ_INSTS_VALU_ADD_F32"], per["SQ_INSTS_VALU_MUL_F32"],
+                       per["SQ_INSTS_VALU_FMA_F64"], per["SQ_INSTS_VALU_ADD_F64"],
+                       per["SQ_INSTS_VALU_MUL_F64"], f32 * pt / secs / 1e12,
+                       f64 * pt / secs / 1e12, cycles / secs / 1e9 if secs else 0.0,
+                       d.get("SQ_INSTS_VALU", 0.0) / (256 * cycles) if cycles else 0.0))
+    with open(out_path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def summarize_counters(fetch_csv, write_csv, out_path, turns_per_launch):
     """Condense two rocprofv3 --pmc CSVs (FETCH_SIZE run, WRITE_SIZE run) into
     HBM bytes per particle-turn for the fused and unfused kernels, scaled by
@@ -1443,6 +1483,8 @@ def main():
                     help="condense rocprofv3 counter CSVs into a profiles/ JSON summary")
     ap.add_argument("--summarize-valu", nargs=3, metavar=("VALU_CSV", "OUT", "K"),
                     help="condense a rocprofv3 SQ_INSTS_VALU* CSV into a markdown table")
+    ap.add_argument("--summarize-valu-f32c", nargs=3, metavar=("VALU_CSV", "OUT", "K"),
+                    help="the same for the FP32 and FP64 counters of --workload counters_f32c")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: libltrk has no multi-GPU path "
@@ -1455,6 +1497,10 @@ def main():
         return
     if args.summarize_valu:
         summarize_valu(args.summarize_valu[0], args.summarize_valu[1], int(args.summarize_valu[2]))
+        return
+    if args.summarize_valu_f32c:
+        summarize_valu_f32c(args.summarize_valu_f32c[0], args.summarize_valu_f32c[1],
+                            int(args.summarize_valu_f32c[2]))
         return
     {"paper": bench_default, "unfused": bench_unfused, "ksweep": bench_ksweep,
      "precision": bench_precision, "batched": bench_batched, "serving": bench_serving,

@@ -71,7 +71,9 @@ extern "C" {
 /* State precisions. */
 #define LTRK_F64 0            /* z, dp in FP64 */
 #define LTRK_F32C 1           /* z, dp as FP32 hi plus FP32 Kahan compensation;
-                                 value = hi - comp. RF phase and moments in FP64 */
+                                 value = hi - comp. RF phase reduction and moments
+                                 in FP64; the sine of the reduced phase in FP32
+                                 (kick relative error <= 1.7e-7; RK4: FP64 sine) */
 
 /* Ring and beam parameters: circumference [m], harmonic number (integer
  * valued, > 0), RF voltage [V], reference momentum p0 c [eV], rest energy

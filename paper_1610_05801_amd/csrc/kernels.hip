@@ -101,9 +101,10 @@ __device__ __forceinline__ void turn_f64(double& z, double& d, const Coeffs& c) 
 // One turn, FP32 + Kahan state. Drift increments are FP32 products of the FP32
 // momentum value with the drift coefficient carried as an FP32 hi + lo pair (a
 // coefficient rounded to FP32 alone would shift the synchrotron tune by up to
-// 2^-25 relative, a systematic phase error); kick increments are FP64 (phase from the FP64 value
-// hi - comp, sin in FP64) rounded once to FP32. RK4 evaluates its stages in
-// FP64 from the FP64 state value and adds FP32-rounded increments.
+// 2^-25 relative, a systematic phase error). Kick increments take the phase
+// reduction in FP64 from the FP64 value hi - comp and the sine in FP32
+// (scaled_sin_f32). RK4 evaluates its stages, sine included, in FP64 from the
+// FP64 state value and adds FP32-rounded increments.
 
 template <int INTEG, bool EXACT>
 __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float& dc,
@@ -113,24 +114,24 @@ __device__ __forceinline__ void turn_f32c(float& zh, float& zc, float& dh, float
     const float v = dh - dc;
     kahan_add(zh, zc, __builtin_fmaf(ndf[0], v, ndf[1] * v));
   };
-  auto kick = [&](const double* q) {
+  auto kick = [&](const float* a) {
     const double zv = static_cast<double>(zh) - static_cast<double>(zc);
-    kahan_add(dh, dc, static_cast<float>(scaled_sin<EXACT>(zv, s, q)));
+    kahan_add(dh, dc, scaled_sin_f32<EXACT>(zv, s, a));
   };
   if constexpr (INTEG == kEulerCromer) {
     drift(c.nd_f[0]);
-    kick(c.kq[0]);
+    kick(c.ka_f[0]);
   } else if constexpr (INTEG == kLeapfrog) {
     drift(c.nd_f[0]);
-    kick(c.kq[0]);
+    kick(c.ka_f[0]);
     drift(c.nd_f[0]);
   } else if constexpr (INTEG == kRuth4) {
     drift(c.nd_f[0]);
-    kick(c.kq[0]);
+    kick(c.ka_f[0]);
     drift(c.nd_f[1]);
-    kick(c.kq[1]);
+    kick(c.ka_f[1]);
     drift(c.nd_f[1]);
-    kick(c.kq[0]);
+    kick(c.ka_f[0]);
     drift(c.nd_f[0]);
   } else if constexpr (INTEG == kRk4) {
     const double z = static_cast<double>(zh) - static_cast<double>(zc);

@@ -48,6 +48,8 @@ struct Coeffs {
                                // |d delta| <= reach_k (in_exact_range)
   float nd_f[2][2];            // nd split into FP32 hi + lo (F32C drift increments:
                                // fma(hi, v, lo * v) carries the coefficient to ~2^-48)
+  float ka_f[2][2];            // kick weight x A x pi split into FP32 hi + lo (F32C
+                               // kicks, the FP32 sine; RK4 F32C keeps the FP64 sine)
 };
 
 // One bunch as the kernels see it.

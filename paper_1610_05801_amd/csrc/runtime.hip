@@ -140,6 +140,9 @@ void make_coeffs(const ltrk_ring& r, int integrator, Coeffs* c) {
   for (int i = 0; i < 2; ++i) {
     c->nd_f[i][0] = static_cast<float>(c->nd[i]);
     c->nd_f[i][1] = static_cast<float>(c->nd[i] - static_cast<double>(c->nd_f[i][0]));
+    const double a = kw[i] * M_PI;
+    c->ka_f[i][0] = static_cast<float>(a);
+    c->ka_f[i][1] = static_cast<float>(a - static_cast<double>(c->ka_f[i][0]));
   }
 }
 

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "ltrk_device.h"
+#include "sinpi32_coeffs.h"
 
 namespace ltrk {
 
@@ -62,26 +63,48 @@ __device__ __forceinline__ KickTerms terms_of(double r, double t, const double* 
   return KickTerms{parity_signed(r, t), p};
 }
 
-__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
+// The reductions alone: r = u - n and a double t whose last mantissa bit is
+// the parity of n.
+struct Reduced {
+  double r, t;
+};
+
+__device__ __forceinline__ Reduced reduce_u(double u) {
   const double n = __builtin_rint(u);
-  return terms_of(u - n, __builtin_fabs(n) + 0x1p52, q);
+  return Reduced{u - n, __builtin_fabs(n) + 0x1p52};
+}
+
+__device__ __forceinline__ Reduced reduce_at(double z, double s) {
+  const double t = __builtin_fma(z, s, kRoundMagic);
+  const double n = t - kRoundMagic;
+  return Reduced{__builtin_fma(z, s, -n), t};
+}
+
+template <bool EXACT>
+__device__ __forceinline__ Reduced reduce_sz(double z, double s) {
+  if constexpr (EXACT)
+    return reduce_at(z, s);
+  else
+    return reduce_u(z * s);
+}
+
+__device__ __forceinline__ KickTerms kick_terms(double u, const double* __restrict__ q) {
+  const Reduced x = reduce_u(u);
+  return terms_of(x.r, x.t, q);
 }
 
 __device__ __forceinline__ KickTerms kick_terms_at(double z, double s,
                                                    const double* __restrict__ q) {
-  const double t = __builtin_fma(z, s, kRoundMagic);
-  const double n = t - kRoundMagic;
-  return terms_of(__builtin_fma(z, s, -n), t, q);
+  const Reduced x = reduce_at(z, s);
+  return terms_of(x.r, x.t, q);
 }
 
 // Kick terms of the phase s z by either reduction.
 template <bool EXACT>
 __device__ __forceinline__ KickTerms kick_terms_sz(double z, double s,
                                                    const double* __restrict__ q) {
-  if constexpr (EXACT)
-    return kick_terms_at(z, s, q);
-  else
-    return kick_terms(z * s, q);
+  const Reduced x = reduce_sz<EXACT>(z, s);
+  return terms_of(x.r, x.t, q);
 }
 
 // scale * sin(pi s z) as one product.
@@ -97,6 +120,32 @@ __device__ __forceinline__ double kicked(double d, double z, double s,
                                         const double* __restrict__ q) {
   const KickTerms k = kick_terms_sz<EXACT>(z, s, q);
   return __builtin_fma(k.r, k.p, d);
+}
+
+// The same sign flip on an FP32 value.
+__device__ __forceinline__ float parity_signed(float v, double t) {
+  const uint32_t tl = __builtin_bit_cast(Words, t).lo;
+  uint32_t o;
+  asm("v_lshl_add_u32 %0, %1, 31, %2" : "=v"(o) : "v"(tl), "v"(__builtin_bit_cast(uint32_t, v)));
+  return __builtin_bit_cast(float, o);
+}
+
+// a * sin(pi s z) in FP32 from the FP64 phase reduction (the F32C kick): r is
+// rounded to FP32 once, sin(pi r) / (pi r) comes from the FP32 polynomial of
+// sinpi32_coeffs.h, and a = a[0] + a[1] (amplitude times pi as two FP32
+// parts, so the kick strength itself is not rounded to FP32: a single FP32
+// amplitude would shift the synchrotron tune by up to 2^-25 relative, a bias
+// that does not average out over turns).
+template <bool EXACT>
+__device__ __forceinline__ float scaled_sin_f32(double z, double s, const float* __restrict__ a) {
+  const Reduced x = reduce_sz<EXACT>(z, s);
+  const float r = static_cast<float>(x.r);
+  const float r2 = r * r;
+  float p = kSinPi32Coeff[kSinPi32Terms - 1];
+#pragma unroll
+  for (int j = kSinPi32Terms - 2; j >= 0; --j) p = __builtin_fmaf(p, r2, kSinPi32Coeff[j]);
+  const float v = parity_signed(r * p, x.t);
+  return __builtin_fmaf(a[0], v, a[1] * v);
 }
 
 // Whether every position a wave reaches in a launch of `turns` turns keeps

@@ -1,8 +1,10 @@
 """FP32 + Kahan-compensated state (LTRK_F32C) against the FP64 oracle.
 
 The state is FP32 (hi, comp) with every increment rounded to FP32 once and
-added with Kahan compensation; the RF phase and sin are FP64 and the moments
-are accumulated in FP64. Error model: each increment carries a relative
+added with Kahan compensation; the RF phase is reduced in FP64, the sine of
+the reduced phase is an FP32 polynomial (the increment's relative error is at
+most 1.7e-7, median 3e-8, against at most 2^-24 = 6e-8 for an FP64 sine
+rounded once to FP32), and the moments are accumulated in FP64. Error model: each increment carries a relative
 rounding of at most 2^-24, the compensated sums add no further error at
 leading order, so after T turns a particle's coordinates differ from FP64 by
 roughly sqrt(T) * 2^-24 * |increment| (random walk), and the resulting

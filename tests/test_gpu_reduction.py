@@ -118,10 +118,11 @@ def test_non_finite_positions_give_nan_momenta(ltrk):
     assert np.all(np.isnan(dp[:3])) and np.isfinite(dp[3])
 
 
-def test_f32c_kick_is_the_fp32_rounding_of_the_exact_kick(ltrk):
-    """F32C: the kick is computed in FP64 from hi - comp and rounded once to
-    FP32, so it is within half an FP32 ulp (2^-24 relative) of the exact kick
-    plus the FP64 budget."""
+def test_f32c_kick_is_within_three_fp32_ulp_of_the_exact_kick(ltrk):
+    """F32C: the phase is reduced in FP64 from hi - comp and the sine of the
+    reduced phase evaluated in FP32 (rounding of r, r^2, four FMA, r * p, the
+    two-part amplitude), so the kick is within 3 FP32 ulp (3 * 2^-24 relative)
+    of the exact kick plus the FP64 budget, and within one ulp on median."""
     z0 = positions(83, 3000, -3.0, 14.0).astype(np.float32)
     z = torch.as_tensor(z0).cuda()
     dp, zc, dc = torch.zeros_like(z), torch.zeros_like(z), torch.zeros_like(z)
@@ -130,4 +131,6 @@ def test_f32c_kick_is_the_fp32_rounding_of_the_exact_kick(ltrk):
     assert np.array_equal(z.cpu().numpy(), z0)
     got = dp.cpu().numpy().astype(np.float64) - dc.cpu().numpy().astype(np.float64)
     want = exact_kick(z0.astype(np.float64))
-    assert np.all(np.abs(got - want) <= 2.0 ** -24 * np.abs(want) + 1e-15 * A)
+    assert np.all(np.abs(got - want) <= 3 * 2.0 ** -24 * np.abs(want) + 1e-15 * A)
+    nz = want != 0
+    assert np.median(np.abs(got - want)[nz] / np.abs(want[nz])) <= 2.0 ** -24
