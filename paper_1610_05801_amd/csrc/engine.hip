@@ -231,14 +231,15 @@ int engine_step(ltrk_engine* e, int k, hipStream_t user, int64_t* advanced) {
   if (act.empty()) return LTRK_OK;
   // Heaviest tiles first (the launch's blocks are dispatched in tile order,
   // so the cheap ones fill in behind and the launch ends on short blocks):
-  // jobs by per-particle-turn cost, a scheme's flops, F32C about 1.6 times
-  // FP64 (FP32/FP64 conversions and Kahan additions); a job's tiles stay
-  // together. The results do not depend on the order.
+  // jobs by per-particle-turn cost, a scheme's flops, F32C about 1.4 times
+  // FP64 (FP32/FP64 conversions and Kahan additions; measured 1.25-1.45 over
+  // the schemes); a job's tiles stay together. The results do not depend on
+  // the order.
   auto unit_cost = [&](int i) {
     const Slot& s = e->slots[i];
     static const double flops[4] = {30.0, 32.0, 76.0, 112.0};
     const double f = s.integrator >= 0 && s.integrator < 4 ? flops[s.integrator] : 32.0;
-    return f * (s.dtype == LTRK_F32C ? 1.6 : 1.0);
+    return f * (s.dtype == LTRK_F32C ? 1.4 : 1.0);
   };
   std::stable_sort(act.begin(), act.end(),
                    [&](int a, int b) { return unit_cost(a) > unit_cost(b); });
