@@ -25,9 +25,9 @@ namespace ltrk {
 namespace {
 
 // 8 particles per lane: one mixed launch runs FP64 and FP32 + Kahan tiles of
-// every scheme, and at 16 its FP32 + Kahan branches would take up to 268
-// VGPRs (one wave per SIMD); single-bunch and batched FP64 calls use 16
-// where it pays.
+// every scheme, and at 16 the FP32 + Kahan Ruth4 tile alone takes 256 VGPRs
+// (its single-bunch kernel ran 35% slower at 16 than at 8); single-bunch and
+// batched FP64 calls use 16 where it pays.
 constexpr int kEnginePpl = 8;
 constexpr int kEngineBlock = 256;
 constexpr int kDepth = 2;  // steps in flight
