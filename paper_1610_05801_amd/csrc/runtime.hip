@@ -1259,7 +1259,7 @@ static int track_6d(double* const* arr, int64_t n, int64_t turns, const ltrk_rf2
   bool default_plan = false;
   ltrk_plan plan = choose_plan(integrator, LTRK_F64, n, false, &default_plan);
   // six FP64 coordinates per particle: 4 or 8 particles per lane (8 takes
-  // ~177 VGPRs and still two waves per SIMD; at 1e6 particles, same box, it
+  // ~177 VGPRs and still two waves per SIMD; at 1e6 particles, on one MI355X, it
   // ran leap-frog 2.42e11 against 2.24e11 with 4 and Ruth4 1.64e11 against
   // 1.51e11, both at 256 turns per launch). The default plan takes at most
   // 256 turns per launch here (with 8 per lane: leap-frog 2.43e11 at 512,
