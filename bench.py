@@ -286,7 +286,9 @@ def bench_default(args):
 
     extras = {}
     if not args.quick:
-        # FP32 + Kahan state on the same workload (2 steps)
+        # FP32 + Kahan state on the same workload (2 steps); its moment rows
+        # against those of the FP64 steps (same initial bunch)
+        m64 = mom.cpu().numpy()
         zh, zc = split_f32c(z0)
         dh, dc = split_f32c(dp0)
         f32 = [torch.as_tensor(a).to(dev) for a in (zh, dh, zc, dc)]
@@ -304,8 +306,16 @@ def bench_default(args):
                     f32_s += (time.perf_counter() - t0) / reps
         v32 = n * T / f32_s
         del f32, f32_run
+        m32 = mom.cpu().numpy()
+        rel = np.abs(m32 - m64) / np.abs(m64)
+        rel[:, 0] = np.abs(m32[:, 0] - m64[:, 0]) / m64[:, 1]   # means over their rms
+        rel[:, 2] = np.abs(m32[:, 2] - m64[:, 2]) / m64[:, 3]
         extras["f32c"] = {"value": v32, "unit": "particle-turns/s", "ms_per_step": f32_s * 1e3,
-                          "ratio_to_f64": v32 / value}
+                          "ratio_to_f64": v32 / value,
+                          "moments_vs_f64_max_rel": dict(zip(
+                              ["mean_z", "rms_z", "mean_dp", "rms_dp", "emit"],
+                              rel.max(axis=0).tolist())),
+                          "note": "max over the 1e4 turns; means relative to their rms"}
         log("f32c: %.4e particle-turns/s" % v32)
         # one launch per turn (HBM-bound form) on the same workload, 1e3 turns
         Tu = min(T, 1000)
