@@ -327,10 +327,9 @@ int ltrk_track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int int
 
 /* Launch plan. turns_per_launch K: turns fused per kernel launch (1 = one
  * launch per turn, the unfused form); block: threads per block (64, 128 or
- * 256); ppl: particles per lane (1, 2, 4, 8 or 16; 16 is used by FP64
- * single-bunch and batched calls only: FP32 + Kahan, extended-map and wake
- * calls take at most 8, extended-map and wake calls at least 4, with the same
- * results as at that value); use_graph: replay the launch
+ * 256); ppl: particles per lane (1, 2, 4, 8 or 16; extended-map and wake
+ * calls take 4 or 8, the nearest of the two, with the same results as at that
+ * value); use_graph: replay the launch
  * sequence from a cached hipGraph (streams other than NULL only). A call of
  * more launches than the environment variable LTRK_MAX_GRAPH_LAUNCHES (read
  * at every call; default 32768, at least 16) is never captured: its launches
@@ -349,8 +348,9 @@ typedef struct ltrk_plan {
  * automatic plans from the tuning cache or the built-in default). EINVAL for
  * values outside the ranges above. Forced and tuned plans are used as given;
  * the built-in default (1024 turns per launch; 8 particles per lane from
- * ~1e5 particles, 16 for FP64 calls where the waves then fill the device's
- * wave slots in fewer rounds, e.g. from 6e6 particles in all) is
+ * ~1e5 particles, 16 for FP64 calls and F32C Euler-Cromer and leap-frog
+ * calls where the waves then fill the device's wave slots in fewer rounds,
+ * e.g. from 6e6 particles in all) is
  * lowered, for calls that compute moments, to the largest power of two (at
  * least 64) whose moment partials of one launch stay within 192 MiB, e.g.
  * 512 turns at 1e7 particles (16 per lane). */
@@ -363,8 +363,8 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out);
 
 /* Time candidate plans on scratch particles of size n (on `stream`,
  * synchronising it): every combination of 32, 128, 256, 512, 1024 and 2048
- * turns per launch, 64, 128 and 256 threads per block and 1, 2, 4 and 8
- * particles per lane (and 16 for LTRK_F64), with moments. Cache the fastest
+ * turns per launch, 64, 128 and 256 threads per block and 1, 2, 4, 8 and 16
+ * particles per lane, with moments. Cache the fastest
  * for single-bunch calls
  * of (device, integrator, dtype, floor(log2 n)). `best` (host, may be NULL)
  * receives it. */
@@ -378,8 +378,8 @@ int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan*
  * descriptors; only each bunch's n, ring and whether it has moments are read,
  * its arrays are not touched): probe bunches of those sizes and rings are
  * tracked on `stream` (synchronised) with every combination of 128, 256, 512
- * and 1024 turns per launch, 64, 128 and 256 threads per block and 2, 4 and 8
- * particles per lane (and 16 for LTRK_F64), and the fastest plan is cached for
+ * and 1024 turns per launch, 64, 128 and 256 threads per block and 2, 4, 8
+ * and 16 particles per lane, and the fastest plan is cached for
  * batched calls of
  * (device, integrator, dtype, floor(log2 of the total particles)). Needs
  * device memory for the probes' state and 4096 moment rows per bunch with

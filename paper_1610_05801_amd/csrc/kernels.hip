@@ -572,9 +572,7 @@ SingleFn single_fn(int pi) {
     case 1: return k_track_single<I, D, 2>;
     case 2: return k_track_single<I, D, 4>;
     case 3: return k_track_single<I, D, 8>;
-    case 4:
-      if constexpr (D == kF64) return k_track_single<I, D, 16>;
-      return nullptr;
+    case 4: return k_track_single<I, D, 16>;
     default: return nullptr;
   }
 }
@@ -586,9 +584,7 @@ TilesFn tiles_fn(int pi) {
     case 1: return k_track_tiles<I, D, 2>;
     case 2: return k_track_tiles<I, D, 4>;
     case 3: return k_track_tiles<I, D, 8>;
-    case 4:
-      if constexpr (D == kF64) return k_track_tiles<I, D, 16>;
-      return nullptr;
+    case 4: return k_track_tiles<I, D, 16>;
     default: return nullptr;
   }
 }

@@ -981,10 +981,9 @@ static int track_single(void* z, void* dp, void* zc, void* dc, int64_t n, int64_
   if ((rc = current_device(&dev))) return rc;
   bool default_plan = false;
   ltrk_plan plan = choose_plan(integrator, dtype, n, false, &default_plan);
-  // extended kernels: 4 or 8 particles per lane; 16 is compiled for the plain
-  // FP64 kernels only
+  // extended kernels: 4 or 8 particles per lane (16 is compiled for the
+  // single-harmonic kernels only)
   if (ext) plan.ppl = std::min(std::max(plan.ppl, 4), 8);
-  if (dtype != LTRK_F64) plan.ppl = std::min(plan.ppl, 8);
   if (mom && default_plan)
     plan.turns_per_launch = static_cast<int32_t>(default_turns_for_partials(
         plan.turns_per_launch,
@@ -1627,8 +1626,6 @@ static int track_batched(const ltrk_bunch* bunches, int nb, int64_t turns, int i
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
   ltrk_plan plan = choose_plan(integrator, dtype, total_n, true);
-  // 16 particles per lane: FP64 tile kernels only
-  if (dtype != LTRK_F64) plan.ppl = std::min(plan.ppl, 8);
   const int wpb = plan.block / kWave;
 
   std::vector<BunchDev> bd(nb);

@@ -87,7 +87,7 @@ int log2_bucket(int64_t n) {
 constexpr int64_t kWaveSlots = 2048;
 constexpr double kCostPerSlot16 = 0.93;
 
-ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool /*batched*/) {
+ltrk_plan default_plan(int integrator, int dtype, int64_t n, bool /*batched*/) {
   ltrk_plan p;
   // 1024 turns per launch: 1.2-1.6% over 512 at 1e6 particles (fewer launch
   // boundaries), while a launch's moment partials (80 MB at 1e6 particles)
@@ -107,18 +107,23 @@ ltrk_plan default_plan(int /*integrator*/, int dtype, int64_t n, bool /*batched*
     p.ppl = 2;
   else
     p.ppl = 1;
-  // 16 particles per lane (FP64 only; a batched call counts the waves of
-  // all its bunches) halve the per-particle
-  // share of the moment reduction and of the partials, and still run two
-  // waves per SIMD; a lane's particles cost ~7% less than at 8 (measured
-  // 1.57e12 against 1.49e12 at 1e7 particles, 1.59e12 against 1.46e12 at
-  // 4e7). The kernels hold two waves per SIMD (the LDS rows, and ~230 VGPRs
-  // at 16), so waves run in rounds of kWaveSlots and a launch lasts
-  // ceil(waves / kWaveSlots) rounds of P particles each: 16 is taken where
-  // that costs less (2e6, 4e6 and from 6e6 particles on; not at 1e6, where it
-  // would leave one wave per SIMD: 1.25e12 against 1.43e12, nor at 3e6 or
-  // 5e6, where the last round would be a small one).
-  if (dtype == LTRK_F64 && p.ppl == 8) {
+  // 16 particles per lane (a batched call counts the waves of all its
+  // bunches) halve the per-particle share of the moment reduction and of the
+  // partials, and still run two waves per SIMD; a lane's particles cost ~7%
+  // less than at 8 (FP64: 1.57e12 against 1.49e12 at 1e7 particles, 1.59e12
+  // against 1.46e12 at 4e7; F32C leap-frog 1.066e12 against 1.003e12 at 1e7).
+  // The kernels hold two waves per SIMD (the LDS rows, and ~230 VGPRs at 16
+  // for FP64, 250 for F32C Euler-Cromer and leap-frog), so waves run in rounds
+  // of kWaveSlots and a launch lasts ceil(waves / kWaveSlots) rounds of P
+  // particles each: 16 is taken where that costs less (2e6, 4e6 and from 6e6
+  // particles on; not at 1e6, where it would leave one wave per SIMD: 1.25e12
+  // against 1.43e12, nor at 3e6 or 5e6, where the last round would be a small
+  // one). Not for F32C Ruth4 and RK4: the single-bunch Ruth4 kernel needs more
+  // than 256 registers at 16 (one wave per SIMD; measured 35% slower at 1e7),
+  // and RK4 was not measured.
+  const bool sixteen = dtype == LTRK_F64 || integrator == LTRK_EULER_CROMER ||
+                       integrator == LTRK_LEAPFROG;
+  if (sixteen && p.ppl == 8) {
     auto rounds = [&](int ppl) { return (waves_for(n, ppl) + kWaveSlots - 1) / kWaveSlots; };
     if (static_cast<double>(rounds(16)) * 16.0 * kCostPerSlot16 <
         static_cast<double>(rounds(8)) * 8.0)
@@ -236,7 +241,7 @@ int autotune(int integrator, int dtype, int64_t n, hipStream_t s, ltrk_plan* bes
   ltrk_plan best{128, 256, 4, 1};
   double best_rate = -1.0;
   const int ppls[5] = {1, 2, 4, 8, 16};
-  const int n_ppls = dtype == LTRK_F64 ? 5 : 4;  // 16: FP64 kernels only
+  const int n_ppls = 5;
   const int blocks[3] = {64, 128, 256};
   const int ks[6] = {32, 128, 256, 512, 1024, 2048};
   for (int ki = 0; ki < 6 && rc == LTRK_OK; ++ki) {
@@ -380,7 +385,7 @@ int autotune_batched(const ltrk_bunch* bunches, int nb, int integrator, int dtyp
   ltrk_plan best{256, 256, 8, 1};
   double best_rate = -1.0;
   const int ppls[4] = {2, 4, 8, 16};
-  const int n_ppls = dtype == LTRK_F64 ? 4 : 3;  // 16: FP64 tile kernels only
+  const int n_ppls = 4;
   const int blocks[3] = {64, 128, 256};
   const int ks[4] = {128, 256, 512, 1024};
   for (int ki = 0; ki < 4 && rc == LTRK_OK; ++ki) {
@@ -443,7 +448,6 @@ int ltrk_get_plan(int integrator, int dtype, int64_t n, ltrk_plan* out) {
   if (!valid_integrator(integrator) || !valid_dtype(dtype) || n < 0)
     return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
   *out = choose_plan(integrator, dtype, n, false);
-  if (dtype != LTRK_F64) out->ppl = std::min(out->ppl, 8);  // as the call does
   return LTRK_OK;
 }
 
@@ -453,7 +457,6 @@ int ltrk_get_plan_batched(int integrator, int dtype, int64_t total_n, ltrk_plan*
   if (!valid_integrator(integrator) || !valid_dtype(dtype) || total_n < 0)
     return fail(LTRK_EINVAL, "invalid integrator, dtype or n");
   *out = choose_plan(integrator, dtype, total_n, true);
-  if (dtype != LTRK_F64) out->ppl = std::min(out->ppl, 8);  // as the call does
   return LTRK_OK;
 }
 

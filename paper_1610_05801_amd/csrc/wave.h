@@ -407,7 +407,8 @@ __device__ __forceinline__ void wave_f64(const BunchDev& b, const Exact& exact, 
 // Launch-shape helpers (host)
 
 // Index of a particles-per-lane value among the compiled ones (1, 2, 4, 8;
-// 16 for the FP64 single-bunch and tile kernels only).
+// 16 for the single-bunch and tile kernels, not the extended-map, wake or
+// engine kernels).
 inline int ppl_index(int ppl) {
   switch (ppl) {
     case 1: return 0;

@@ -57,7 +57,10 @@ def test_default_plan_follows_the_moment_partials(ltrk):
     plan = ltrk.ltrk_get_plan("leapfrog", "f64", 10_000_000)
     assert plan["turns_per_launch"] == 1024 and plan["ppl"] == 16
     assert ltrk.ltrk_get_plan("leapfrog", "f64", 1_000_000)["ppl"] == 8
-    assert ltrk.ltrk_get_plan("leapfrog", "f32c", 10_000_000)["ppl"] == 8
+    # F32C: 16 for Euler-Cromer and leap-frog, 8 for Ruth4 and RK4
+    assert ltrk.ltrk_get_plan("leapfrog", "f32c", 10_000_000)["ppl"] == 16
+    assert ltrk.ltrk_get_plan("ruth4", "f32c", 10_000_000)["ppl"] == 8
+    assert ltrk.ltrk_get_plan("rk4", "f32c", 10_000_000)["ppl"] == 8
     assert launches(10_000_000, 1024, True) == 2
     assert launches(10_000_000, 1024, False) == 1
     assert launches(1_000_000, 2048, True) == 2
