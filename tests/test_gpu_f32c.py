@@ -1,16 +1,17 @@
 """FP32 + Kahan-compensated state (LTRK_F32C) against the FP64 oracle.
 
-The state is FP32 (hi, comp) with every increment rounded to FP32 once and
-added with Kahan compensation; the RF phase is reduced in FP64, the sine of
-the reduced phase is an FP32 polynomial (the increment's relative error is at
-most 1.7e-7, median 3e-8, against at most 2^-24 = 6e-8 for an FP64 sine
-rounded once to FP32), and the moments are accumulated in FP64. Error model: each increment carries a relative
-rounding of at most 2^-24, the compensated sums add no further error at
+The state is FP32 (hi, comp) with every increment an FP32 value added with
+Kahan compensation; the RF phase is reduced in FP64, the sine of the reduced
+phase is an FP32 polynomial (the kick increment's relative error is at most
+1.7e-7, median 3e-8, against at most 2^-24 = 6e-8 for an FP64 sine rounded
+once to FP32), and the moments are accumulated in FP64. Error model: each
+increment carries a relative error of a few 2^-24 (the drifts one rounding,
+the kicks up to 3 FP32 ulp), the compensated sums add no further error at
 leading order, so after T turns a particle's coordinates differ from FP64 by
-roughly sqrt(T) * 2^-24 * |increment| (random walk), and the resulting
-amplitude error turns into a phase error growing ~T through the amplitude
-dependence of the synchrotron tune. The bounds below are that estimate with
-a safety factor, checked at 1e3 turns on the small seeded bunch.
+roughly sqrt(T) * 2^-24 * |increment| times a small factor (random walk), and
+the resulting amplitude error turns into a phase error growing ~T through the
+amplitude dependence of the synchrotron tune. The bounds below are that
+estimate with a safety factor, checked at 1e3 turns on the small seeded bunch.
 """
 import numpy as np
 import pytest
